@@ -1,0 +1,164 @@
+/*
+ * recon.h - C ABI of the MI355X (gfx950) Fourier-slice insertion library.
+ *
+ * The library implements the data-parallel core of 3D Fourier reconstruction
+ * as the paper states it in Sect. 5.3.1, Algorithm 1 ("3D reconstruction"):
+ * zero-initialise a complex Fourier volume G and a weight volume W in GPU
+ * memory, insert batches of 2D Fourier samples (slices) of arbitrary
+ * orientation into G and W, and apply the weights W to G.  The insertion step
+ * and its interpolation weights are described in Sect. 4.2 ("3D Fourier
+ * Reconstruction"); the interpolation window used here is the Kaiser-Bessel
+ * blob of radius a, taper alpha and order m, tabulated in squared distance.
+ *
+ * Conventions (all sizes in elements unless stated):
+ *   h = n / 2.  The volume is the centered box {-h..h}^3, stored [z][y][x]
+ *   with x fastest, index = coordinate + h; G is complex64 (interleaved
+ *   float re, im), W is float32, V (output of recon_finalize) is complex64.
+ *   A slice is the centered 2D DFT of a real projection image in Hermitian
+ *   half-plane layout [row = ky + h][kx], kx in [0, h], complex64 (or a pair
+ *   of 16-bit floats per component, see recon_slice_dtype).  Its full-plane
+ *   value is F(k) for kx > 0 or (kx = 0 and ky >= 0), otherwise conj F(-k);
+ *   stored entries with kx = 0, ky < 0 are never read.  Samples inserted are
+ *   those with kx^2 + ky^2 < r_max^2.  An orientation is a quaternion
+ *   (w, x, y, z), scalar first, normalised before use; sample k of a slice
+ *   with rotation R sits at volume frequency R (kx, ky, 0)^T and adds
+ *   b(d^2) F(k) to G and b(d^2) to W at every voxel within distance a.
+ *
+ * Memory: every device buffer is allocated by the caller and borrowed.
+ * All work is enqueued on the context's HIP stream and is asynchronous with
+ * respect to the host unless a function says otherwise; buffers passed to a
+ * call must stay valid until the stream has passed that call.  Functions
+ * return a recon_status; none throws across the ABI.  The text of the last
+ * error of the calling thread is available from recon_last_error().
+ * A context is not thread-safe: calls on one context must be serialised.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum recon_status {
+    RECON_OK = 0,
+    RECON_EINVAL = -1,   /* invalid argument (null pointer, size out of range) */
+    RECON_ENOMEM = -2,   /* workspace too small, or host allocation failed */
+    RECON_EDEVICE = -3,  /* HIP runtime error; text in recon_last_error() */
+    RECON_ECONFIG = -4   /* kernel configuration not runnable on this device */
+} recon_status;
+
+/* Storage type of slice samples. */
+typedef enum recon_slice_dtype {
+    RECON_SLICE_C64 = 0,   /* complex64: float re, float im (8 bytes/sample) */
+    RECON_SLICE_F16 = 1,   /* IEEE half re, im, times a per-slice FP32 scale */
+    RECON_SLICE_BF16 = 2   /* bfloat16 re, im (no scale needed) */
+} recon_slice_dtype;
+
+/* Problem description.  Fill with recon_default_params() and override. */
+typedef struct recon_params {
+    int32_t n;            /* slice edge; even, 4 <= n <= 1024; volume (n+1)^3 */
+    float blob_radius;    /* a, 0 < a <= 2.95 (default 1.9) */
+    float blob_alpha;     /* alpha >= 0 (default 15) */
+    int32_t blob_order;   /* m, 0 <= m <= 8 (default 0) */
+    int32_t table_size;   /* N, 2 <= N <= 65536 (default 10000) */
+    int32_t table_lerp;   /* 1: linear interpolation in the table (default), 0: truncation */
+    float r_max;          /* 0 < r_max <= n/2 (default n/2) */
+    int32_t slice_dtype;  /* recon_slice_dtype (default RECON_SLICE_C64) */
+    int32_t max_batch;    /* largest count passed to recon_insert_batch (default 1500) */
+} recon_params;
+
+/* Kernel variants of the insertion step. */
+typedef enum recon_variant {
+    RECON_VARIANT_AUTO = 0,    /* library choice (currently the binned gather) */
+    RECON_VARIANT_NAIVE = 1,   /* one thread per voxel, every slice, global reads */
+    RECON_VARIANT_BINNED = 2   /* tile-binned, LDS-staged gather (default) */
+} recon_variant;
+
+/* Tuning knobs of the insertion kernels (the paper's tuning-space idea,
+ * Sect. 4.2 "3D Fourier Reconstruction" and Table 3: work-group size, work
+ * mapping inside tiles of samples, weight source).  Zero in any field means
+ * "library default".  Invalid combinations are rejected with RECON_ECONFIG. */
+typedef struct recon_config {
+    int32_t variant;          /* recon_variant */
+    int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8 or 16 */
+    int32_t group;            /* slices staged per LDS group (binned): 1..16 */
+    int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 */
+    int32_t split;            /* max slice-range splits of one tile (binned): 1..64 */
+    int32_t reserved[11];
+} recon_config;
+
+typedef struct recon_ctx recon_ctx;
+
+/* Default parameters for slice edge n (a = 1.9, alpha = 15, m = 0,
+ * N = 10000, lerp, r_max = n/2, complex64, max_batch = 1500). */
+recon_status recon_default_params(int32_t n, recon_params *out);
+
+/* Sizes in bytes of the caller-allocated buffers for these parameters:
+ * G (complex64 (n+1)^3), W (float32 (n+1)^3) and the device workspace
+ * (blob table, per-slice orientations, bins, partial sums, counters).
+ * Any output pointer may be NULL. */
+recon_status recon_query_sizes(const recon_params *p, size_t *g_bytes, size_t *w_bytes,
+                               size_t *ws_bytes);
+
+/* Algorithm 1, first two steps: validates p, builds the blob table on the
+ * host in FP64 and uploads it (FP32) into the workspace, and zeroes G and W
+ * on `stream` (a hipStream_t; NULL = the null stream).  d_G, d_W and d_ws
+ * must be device memory of at least the sizes from recon_query_sizes, 256-byte
+ * aligned, and must outlive the context.  This call synchronises `stream`
+ * once before returning.  On success *out receives a new context. */
+recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
+                        size_t ws_bytes, void *stream, recon_ctx **out);
+
+/* Zeroes G and W again and clears the slice counters (asynchronous). */
+recon_status recon_reset(recon_ctx *ctx);
+
+/* Algorithm 1, insertion step (Sect. 4.2, "3D Fourier Reconstruction"):
+ * inserts `count` slices into G and W.  d_slices: device [count][n][n/2+1]
+ * samples of the context's slice_dtype.  d_scales: device float[count]
+ * multiplying each slice (required for RECON_SLICE_F16, may be NULL
+ * otherwise, meaning 1).  d_quats: device float[count][4] (w, x, y, z).
+ * 0 <= count <= max_batch; count = 0 is a no-op.  A quaternion that is zero
+ * or not finite makes its slice contribute nothing; such slices are counted
+ * (recon_stats).  Only the half box x >= 0 of G and W is accumulated here;
+ * recon_finalize completes the x < 0 half from Hermitian symmetry. */
+recon_status recon_insert_batch(recon_ctx *ctx, const void *d_slices, const float *d_scales,
+                                const float *d_quats, int32_t count);
+
+/* Algorithm 1, last step ("apply weights W to G"): fills the x < 0 half of G
+ * and W from their Hermitian mirror (G(-v) = conj G(v), W(-v) = W(v)) and
+ * writes V = G / W (divided in FP64) where W > w_threshold, else 0, into the
+ * caller's device buffer d_V (complex64 (n+1)^3; may be NULL to only mirror).
+ * Non-destructive: more slices may be inserted afterwards. */
+recon_status recon_finalize(recon_ctx *ctx, void *d_V, float w_threshold);
+
+/* Selects insertion-kernel knobs (NULL restores the defaults).  Checks the
+ * configuration against the device's limits; RECON_ECONFIG if infeasible. */
+recon_status recon_set_config(recon_ctx *ctx, const recon_config *cfg);
+
+/* Current (resolved) knobs. */
+recon_status recon_get_config(const recon_ctx *ctx, recon_config *cfg);
+
+/* Replaces the stream used for subsequent calls. */
+recon_status recon_set_stream(recon_ctx *ctx, void *stream);
+
+/* Slices inserted so far and slices rejected for a bad quaternion.
+ * Synchronises the context's stream. */
+recon_status recon_stats(recon_ctx *ctx, uint64_t *slices_inserted, uint64_t *slices_rejected);
+
+/* Releases the context (not the caller's buffers).  NULL is ignored. */
+void recon_destroy(recon_ctx *ctx);
+
+/* Last error text of the calling thread ("" if none). */
+const char *recon_last_error(void);
+
+/* Library version string. */
+const char *recon_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECON_H */

@@ -1,0 +1,65 @@
+// Device-side declarations shared by the gfx950 kernels and their host
+// launchers (internal to librecon.so; the public interface is include/recon.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace recon {
+
+// Geometry and blob constants of one reconstruction, passed by value.
+struct Geom {
+    int n;          // slice edge (even)
+    int h;          // n / 2
+    int dim;        // n + 1, volume edge
+    int sw;         // h + 1, stored half-plane row length
+    float a;        // blob radius
+    float a2;       // a * a
+    float tscale;   // (N - 1) / a^2 : table index per unit squared distance
+    int N;          // table entries
+    float r2max;    // r_max^2 : samples with kx^2 + ky^2 < r2max are inserted
+};
+
+// Per-slice orientation record written by the prep kernel (64 bytes).
+// e1, e2 are the images of the slice's x and y axes in the volume, e3 the
+// plane normal (columns of R).  e1.w is 1 for a usable slice, 0 otherwise.
+struct Orient {
+    float4 e1, e2, e3, pad;
+};
+
+// Workspace counters (device, 256 bytes at the start of the workspace).
+struct Counters {
+    unsigned long long inserted;   // slices passed to the insertion kernels
+    unsigned long long rejected;   // slices with zero / non-finite quaternion
+    unsigned int queue;            // work-queue head of the persistent kernel
+    unsigned int pad[59];
+};
+
+// Work item of the binned kernel: one 4x4x4 voxel tile and one slice range.
+struct Item {
+    int tile;      // tile index (tx + TX * (ty + TY * tz))
+    int part;      // k-th of nparts slice ranges
+    int nparts;    // number of ranges the tile's slices are split into
+    int slot;      // partial-sum slot (when nparts > 1), else -1
+};
+
+// Host launchers (defined in kernels.hip).
+hipError_t launch_zero(float *p, size_t count, hipStream_t st);
+hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr,
+                       hipStream_t st);
+hipError_t launch_insert_naive(const Geom &g, bool lerp, const float2 *slices,
+                               const Orient *orient, int count, const float2 *table,
+                               int inner_chunk, int waves_per_block, float2 *G, float *W,
+                               hipStream_t st);
+hipError_t launch_insert_binned(const Geom &g, bool lerp, const float2 *slices,
+                                const Orient *orient, int count, const float2 *table,
+                                const Item *items, int nitems, float4 *partials,
+                                int inner_chunk, int blocks, int waves_per_block,
+                                Counters *ctr, float2 *G, float *W, hipStream_t st);
+hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
+                                  const float4 *partials, float2 *G, float *W,
+                                  hipStream_t st);
+hipError_t launch_finalize(const Geom &g, float2 *G, float *W, float2 *V, float thr,
+                           hipStream_t st);
+
+}  // namespace recon

@@ -1,0 +1,456 @@
+// Host side of librecon.so: the C ABI declared in include/recon.h.
+//
+// Responsibilities: argument validation, the FP64 blob table (the paper lets
+// the interpolation weights be precomputed, Sect. 4.2 "3D Fourier
+// Reconstruction"), the workspace layout, the static work plan of the binned
+// kernel (tiles, slice-range splits, cost order) and kernel dispatch on the
+// caller's stream.  No device memory is allocated here: G, W, V and the
+// workspace belong to the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/recon.h"
+#include "kernels.hpp"
+
+using recon::Counters;
+using recon::Geom;
+using recon::Item;
+using recon::Orient;
+
+namespace {
+
+thread_local std::string g_err;
+
+recon_status fail(recon_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+recon_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RECON_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// I_m(x) by its power series sum_j (x/2)^(2j+m) / (j! (j+m)!), in FP64.
+double bessel_i(int m, double x)
+{
+    const double half = 0.5 * x, q = half * half;
+    double term = 1.0;
+    for (int j = 1; j <= m; ++j) term *= half / j;
+    double total = term;
+    for (int j = 1; j < 400; ++j) {
+        term *= q / (static_cast<double>(j) * (j + m));
+        total += term;
+        if (term <= 1e-18 * total) break;
+    }
+    return total;
+}
+
+// Kaiser-Bessel blob normalised to b(0) = 1, as a function of squared distance.
+double kb_blob(double d2, double a, double alpha, int m)
+{
+    if (d2 > a * a) return 0.0;
+    double s = 1.0 - d2 / (a * a);
+    if (s < 0.0) s = 0.0;
+    const double scale = m == 0 ? 1.0 : std::pow(s, 0.5 * m);
+    return scale * bessel_i(m, alpha * std::sqrt(s)) / bessel_i(m, alpha);
+}
+
+recon_status validate(const recon_params *p)
+{
+    if (!p) return fail(RECON_EINVAL, "params is NULL");
+    if (p->n < 4 || p->n > 1024 || (p->n & 1))
+        return fail(RECON_EINVAL, "n must be even and in [4, 1024] (got %d)", p->n);
+    if (!(p->blob_radius > 0.0f) || p->blob_radius > 2.95f)
+        return fail(RECON_EINVAL, "blob_radius must be in (0, 2.95] (got %g)", p->blob_radius);
+    if (!(p->blob_alpha >= 0.0f) || !std::isfinite(p->blob_alpha) || p->blob_alpha > 60.0f)
+        return fail(RECON_EINVAL, "blob_alpha must be in [0, 60] (got %g)", p->blob_alpha);
+    if (p->blob_order < 0 || p->blob_order > 8)
+        return fail(RECON_EINVAL, "blob_order must be in [0, 8] (got %d)", p->blob_order);
+    if (p->table_size < 2 || p->table_size > 65536)
+        return fail(RECON_EINVAL, "table_size must be in [2, 65536] (got %d)", p->table_size);
+    if (p->table_lerp != 0 && p->table_lerp != 1)
+        return fail(RECON_EINVAL, "table_lerp must be 0 or 1");
+    if (!(p->r_max > 0.0f) || p->r_max > 0.5f * p->n)
+        return fail(RECON_EINVAL, "r_max must be in (0, n/2] (got %g)", p->r_max);
+    if (p->slice_dtype != RECON_SLICE_C64)
+        return fail(RECON_EINVAL, "slice_dtype %d is not supported by this build", p->slice_dtype);
+    if (p->max_batch < 1 || p->max_batch > (1 << 24))
+        return fail(RECON_EINVAL, "max_batch must be in [1, 2^24] (got %d)", p->max_batch);
+    return RECON_OK;
+}
+
+// ---------------------------------------------------------------------------
+// static work plan of the binned kernel
+// ---------------------------------------------------------------------------
+struct Plan {
+    std::vector<Item> items;
+    int nslots = 0;
+};
+
+// Tiles of 4x4x4 voxels over the half box x in [0, h], y, z in [-h, h].
+// A tile at centre distance r sees, for uniformly distributed slice normals,
+// about min(1, (a + 2.6) / r) of the slices; tiles whose every voxel is out
+// of reach of the disk |k| < r_max are dropped.  Heavy tiles are split into
+// up to `split` slice ranges so that no item costs much more than `target`
+// slice visits; items are ordered by decreasing estimated cost.
+Plan make_plan(const recon_params &p, int split)
+{
+    Plan plan;
+    const int h = p.n / 2, dim = p.n + 1;
+    const int TX = (h + 1 + 3) / 4, TY = (dim + 3) / 4, TZ = TY;
+    const double a = p.blob_radius, reach = p.r_max + a + 2.6;
+    struct Est { int tile; double cost; };
+    std::vector<Est> tiles;
+    double total = 0.0;
+    for (int tz = 0; tz < TZ; ++tz)
+        for (int ty = 0; ty < TY; ++ty)
+            for (int tx = 0; tx < TX; ++tx) {
+                const double cx = 4.0 * tx + 1.5, cy = 4.0 * ty + 1.5 - h, cz = 4.0 * tz + 1.5 - h;
+                const double r = std::sqrt(cx * cx + cy * cy + cz * cz);
+                if (r > reach) continue;
+                const double frac = std::min(1.0, (a + 2.6) / std::max(r, 1e-9));
+                const double cost = frac * p.max_batch;
+                tiles.push_back({tx + TX * (ty + TY * tz), cost});
+                total += cost;
+            }
+    // target item cost: 1/8 of the mean cost per wave slot of a 256-CU device
+    // running 16 waves per CU, but never below 48 slice visits
+    const double target = std::max(48.0, total / (256.0 * 16.0 * 8.0));
+    struct Tmp { Item it; double cost; };
+    std::vector<Tmp> tmp;
+    for (const Est &e : tiles) {
+        int np = static_cast<int>(std::ceil(e.cost / target));
+        np = std::max(1, std::min(np, split));
+        np = std::min(np, std::max(1, p.max_batch));
+        const int slot = np > 1 ? plan.nslots : -1;
+        if (np > 1) plan.nslots += np;
+        for (int k = 0; k < np; ++k) tmp.push_back({{e.tile, k, np, np > 1 ? slot + k : -1}, e.cost / np});
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
+    plan.items.reserve(tmp.size());
+    for (const Tmp &t : tmp) plan.items.push_back(t.it);
+    return plan;
+}
+
+constexpr int kMaxSplit = 64;
+
+struct Layout {
+    size_t ctr = 0, table = 0, orient = 0, items = 0, partials = 0, total = 0;
+};
+
+Layout layout_for(const recon_params &p, int nitems, int nslots)
+{
+    Layout L;
+    size_t off = 0;
+    L.ctr = off;
+    off = align_up(off + sizeof(Counters), 256);
+    L.table = off;
+    off = align_up(off + static_cast<size_t>(p.table_size) * sizeof(float2), 256);
+    L.orient = off;
+    off = align_up(off + static_cast<size_t>(p.max_batch) * sizeof(Orient), 256);
+    L.items = off;
+    off = align_up(off + static_cast<size_t>(nitems) * sizeof(Item), 256);
+    L.partials = off;
+    off = align_up(off + static_cast<size_t>(nslots) * 64 * sizeof(float4), 256);
+    L.total = off;
+    return L;
+}
+
+recon_config default_config()
+{
+    recon_config c;
+    std::memset(&c, 0, sizeof(c));
+    c.variant = RECON_VARIANT_BINNED;
+    c.waves_per_block = 16;
+    c.group = 1;
+    c.inner_chunk = 32;
+    c.split = 16;
+    return c;
+}
+
+}  // namespace
+
+struct recon_ctx {
+    recon_params p;
+    Geom g;
+    hipStream_t stream;
+    float2 *G;
+    float *W;
+    unsigned char *ws;
+    size_t ws_bytes;
+    Layout L;
+    recon_config cfg;
+    Plan plan;           // plan for cfg.split
+    int device;
+    int num_cu;
+    size_t max_lds;
+    int max_threads;
+};
+
+extern "C" {
+
+const char *recon_last_error(void) { return g_err.c_str(); }
+
+const char *recon_version(void) { return "recon-mi355x 0.1 (gfx950)"; }
+
+recon_status recon_default_params(int32_t n, recon_params *out)
+{
+    if (!out) return fail(RECON_EINVAL, "out is NULL");
+    out->n = n;
+    out->blob_radius = 1.9f;
+    out->blob_alpha = 15.0f;
+    out->blob_order = 0;
+    out->table_size = 10000;
+    out->table_lerp = 1;
+    out->r_max = 0.5f * static_cast<float>(n);
+    out->slice_dtype = RECON_SLICE_C64;
+    out->max_batch = 1500;
+    return RECON_OK;
+}
+
+recon_status recon_query_sizes(const recon_params *p, size_t *g_bytes, size_t *w_bytes, size_t *ws_bytes)
+{
+    recon_status st = validate(p);
+    if (st != RECON_OK) return st;
+    const size_t dim = static_cast<size_t>(p->n) + 1;
+    const size_t nvox = dim * dim * dim;
+    if (g_bytes) *g_bytes = nvox * sizeof(float2);
+    if (w_bytes) *w_bytes = nvox * sizeof(float);
+    if (ws_bytes) {
+        Plan worst = make_plan(*p, kMaxSplit);
+        *ws_bytes = layout_for(*p, static_cast<int>(worst.items.size()), worst.nslots).total;
+    }
+    return RECON_OK;
+}
+
+static recon_status upload_plan(recon_ctx *c)
+{
+    if (c->plan.items.empty()) return RECON_OK;
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.items, c->plan.items.data(),
+                                  c->plan.items.size() * sizeof(Item), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "upload work plan");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "upload work plan (sync)");
+    return RECON_OK;
+}
+
+recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws, size_t ws_bytes,
+                        void *stream, recon_ctx **out)
+{
+    if (!out) return fail(RECON_EINVAL, "out is NULL");
+    *out = nullptr;
+    recon_status st = validate(p);
+    if (st != RECON_OK) return st;
+    if (!d_G || !d_W || !d_ws) return fail(RECON_EINVAL, "G, W and workspace must be non-NULL");
+    if ((reinterpret_cast<uintptr_t>(d_G) | reinterpret_cast<uintptr_t>(d_W) |
+         reinterpret_cast<uintptr_t>(d_ws)) & 255u)
+        return fail(RECON_EINVAL, "G, W and workspace must be 256-byte aligned");
+    size_t need = 0;
+    recon_query_sizes(p, nullptr, nullptr, &need);
+    if (ws_bytes < need)
+        return fail(RECON_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+
+    recon_ctx *c = new (std::nothrow) recon_ctx();
+    if (!c) return fail(RECON_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->G = static_cast<float2 *>(d_G);
+    c->W = static_cast<float *>(d_W);
+    c->ws = static_cast<unsigned char *>(d_ws);
+    c->ws_bytes = ws_bytes;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->cfg = default_config();
+
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, c->device);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDeviceProperties"); }
+    c->num_cu = prop.multiProcessorCount;
+    c->max_lds = prop.sharedMemPerBlock;
+    c->max_threads = prop.maxThreadsPerBlock;
+    if (static_cast<size_t>(p->table_size) * sizeof(float2) > c->max_lds)
+        c->cfg.variant = RECON_VARIANT_NAIVE;   // table cannot be staged in LDS
+
+    const int h = p->n / 2;
+    c->g.n = p->n;
+    c->g.h = h;
+    c->g.dim = p->n + 1;
+    c->g.sw = h + 1;
+    c->g.a = p->blob_radius;
+    c->g.a2 = p->blob_radius * p->blob_radius;
+    c->g.N = p->table_size;
+    c->g.tscale = static_cast<float>((p->table_size - 1) /
+                                     (static_cast<double>(p->blob_radius) * p->blob_radius));
+    c->g.r2max = p->r_max * p->r_max;
+
+    Plan worst = make_plan(*p, kMaxSplit);
+    c->L = layout_for(*p, static_cast<int>(worst.items.size()), worst.nslots);
+    c->plan = make_plan(*p, c->cfg.split);
+
+    // blob table: entry i = (T[i], T[i+1] - T[i]), T[i] = b(i a^2 / (N-1)), built in FP64
+    const int N = p->table_size;
+    std::vector<double> T(N);
+    const double a = p->blob_radius;
+    for (int i = 0; i < N; ++i)
+        T[i] = kb_blob(static_cast<double>(i) * a * a / (N - 1), a, p->blob_alpha, p->blob_order);
+    std::vector<float2> tab(N);
+    for (int i = 0; i < N; ++i) {
+        const double next = i + 1 < N ? T[i + 1] : T[i];
+        tab[i] = make_float2(static_cast<float>(T[i]), static_cast<float>(next - T[i]));
+    }
+    e = hipMemcpyAsync(c->ws + c->L.table, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "upload blob table"); }
+    // counters
+    e = recon::launch_zero(reinterpret_cast<float *>(c->ws + c->L.ctr), sizeof(Counters) / sizeof(float),
+                           c->stream);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "clear counters"); }
+    const size_t nvox = static_cast<size_t>(c->g.dim) * c->g.dim * c->g.dim;
+    e = recon::launch_zero(reinterpret_cast<float *>(c->G), 2 * nvox, c->stream);
+    if (e == hipSuccess) e = recon::launch_zero(c->W, nvox, c->stream);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "zero G, W"); }
+    st = upload_plan(c);   // synchronises the stream (also covers the table copy)
+    if (st != RECON_OK) { delete c; return st; }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "recon_init sync"); }
+    *out = c;
+    return RECON_OK;
+}
+
+recon_status recon_reset(recon_ctx *c)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    const size_t nvox = static_cast<size_t>(c->g.dim) * c->g.dim * c->g.dim;
+    hipError_t e = recon::launch_zero(reinterpret_cast<float *>(c->G), 2 * nvox, c->stream);
+    if (e == hipSuccess) e = recon::launch_zero(c->W, nvox, c->stream);
+    if (e == hipSuccess)
+        e = recon::launch_zero(reinterpret_cast<float *>(c->ws + c->L.ctr), sizeof(Counters) / sizeof(float),
+                               c->stream);
+    if (e != hipSuccess) return hip_fail(e, "recon_reset");
+    return RECON_OK;
+}
+
+recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float *d_scales, const float *d_quats,
+                                int32_t count)
+{
+    (void)d_scales;
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    if (count < 0 || count > c->p.max_batch)
+        return fail(RECON_EINVAL, "count must be in [0, max_batch=%d] (got %d)", c->p.max_batch, count);
+    if (count == 0) return RECON_OK;
+    if (!d_slices || !d_quats) return fail(RECON_EINVAL, "slices and quaternions must be non-NULL");
+    Counters *ctr = reinterpret_cast<Counters *>(c->ws + c->L.ctr);
+    Orient *orient = reinterpret_cast<Orient *>(c->ws + c->L.orient);
+    const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
+    const float2 *slices = static_cast<const float2 *>(d_slices);
+    hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
+    if (c->cfg.variant == RECON_VARIANT_NAIVE) {
+        e = recon::launch_insert_naive(c->g, c->p.table_lerp != 0, slices, orient, count, table,
+                                       c->cfg.inner_chunk, c->cfg.waves_per_block, c->G, c->W, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "naive insert kernel launch");
+        return RECON_OK;
+    }
+    const Item *items = reinterpret_cast<const Item *>(c->ws + c->L.items);
+    float4 *partials = reinterpret_cast<float4 *>(c->ws + c->L.partials);
+    const int nitems = static_cast<int>(c->plan.items.size());
+    const int blocks = c->num_cu;
+    e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
+                                    partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
+                                    c->W, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "binned insert kernel launch");
+    if (c->plan.nslots > 0) {
+        e = recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
+    }
+    return RECON_OK;
+}
+
+recon_status recon_finalize(recon_ctx *c, void *d_V, float w_threshold)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    if (!(w_threshold >= 0.0f) || !std::isfinite(w_threshold))
+        return fail(RECON_EINVAL, "w_threshold must be finite and >= 0");
+    if (d_V && (reinterpret_cast<uintptr_t>(d_V) & 7u)) return fail(RECON_EINVAL, "V must be 8-byte aligned");
+    hipError_t e = recon::launch_finalize(c->g, c->G, c->W, static_cast<float2 *>(d_V), w_threshold, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+    return RECON_OK;
+}
+
+recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    recon_config d = default_config();
+    recon_config n = cfg ? *cfg : d;
+    if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
+    if (n.waves_per_block == 0) n.waves_per_block = d.waves_per_block;
+    if (n.group == 0) n.group = d.group;
+    if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
+    if (n.split == 0) n.split = d.split;
+    if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED)
+        return fail(RECON_ECONFIG, "unknown variant %d", n.variant);
+    const int wpb = n.waves_per_block;
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16)
+        return fail(RECON_ECONFIG, "waves_per_block must be 1, 2, 4, 8 or 16");
+    if (64 * wpb > c->max_threads) return fail(RECON_ECONFIG, "work-group of %d threads exceeds device", 64 * wpb);
+    if (n.group < 1 || n.group > 16) return fail(RECON_ECONFIG, "group must be in [1, 16]");
+    if (n.inner_chunk < 1 || n.inner_chunk > 256) return fail(RECON_ECONFIG, "inner_chunk must be in [1, 256]");
+    if (n.split < 1 || n.split > kMaxSplit) return fail(RECON_ECONFIG, "split must be in [1, %d]", kMaxSplit);
+    if (n.variant == RECON_VARIANT_BINNED &&
+        static_cast<size_t>(c->p.table_size) * sizeof(float2) > c->max_lds)
+        return fail(RECON_ECONFIG, "blob table of %d entries does not fit in LDS", c->p.table_size);
+    const bool replan = n.split != c->cfg.split;
+    c->cfg = n;
+    if (replan) {
+        c->plan = make_plan(c->p, n.split);
+        return upload_plan(c);
+    }
+    return RECON_OK;
+}
+
+recon_status recon_get_config(const recon_ctx *c, recon_config *cfg)
+{
+    if (!c || !cfg) return fail(RECON_EINVAL, "NULL argument");
+    *cfg = c->cfg;
+    return RECON_OK;
+}
+
+recon_status recon_set_stream(recon_ctx *c, void *stream)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    c->stream = static_cast<hipStream_t>(stream);
+    return RECON_OK;
+}
+
+recon_status recon_stats(recon_ctx *c, uint64_t *inserted, uint64_t *rejected)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    Counters h;
+    hipError_t e = hipMemcpyAsync(&h, c->ws + c->L.ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "recon_stats");
+    if (inserted) *inserted = h.inserted;
+    if (rejected) *rejected = h.rejected;
+    return RECON_OK;
+}
+
+void recon_destroy(recon_ctx *c) { delete c; }
+
+}  // extern "C"

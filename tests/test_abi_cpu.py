@@ -1,0 +1,88 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/recon.h, and validates parameters on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "recon.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:recon_status|void|const char\s*\*)\s*\*?\s*(recon_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def recon():
+    from paper_1910_08498_amd import recon as r
+    if not os.path.exists(r.LIB_PATH):
+        pytest.fail("librecon.so is not built (run __graft_entry__.build())")
+    r.load_library()
+    return r
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for must in ("recon_init", "recon_insert_batch", "recon_finalize", "recon_query_sizes",
+                 "recon_destroy", "recon_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(recon):
+    lib = ctypes.CDLL(recon.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_params_and_sizes(recon):
+    p = recon.recon_default_params(128)
+    assert p.n == 128 and p.max_batch == 1500 and p.table_size == 10000
+    assert abs(p.blob_radius - 1.9) < 1e-6 and p.blob_alpha == 15.0 and p.r_max == 64.0
+    g, w, ws = recon.recon_query_sizes(p)
+    assert g == 129 ** 3 * 8 and w == 129 ** 3 * 4
+    # table + orientations + plan at least
+    assert ws >= 10000 * 8 + 1500 * 64
+    p.max_batch = 3000
+    assert recon.recon_query_sizes(p)[2] > ws
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 3.5),
+    ("blob_alpha", -1.0), ("blob_order", 9), ("table_size", 1), ("table_lerp", 2),
+    ("r_max", 64.5), ("r_max", 0.0), ("max_batch", 0), ("slice_dtype", 7),
+])
+def test_invalid_params_rejected(recon, field, value):
+    p = recon.recon_default_params(128)
+    setattr(p, field, value)
+    with pytest.raises(recon.ReconError) as ei:
+        recon.recon_query_sizes(p)
+    assert ei.value.status == recon.RECON_EINVAL
+    assert recon.load_library().recon_last_error().decode() != ""
+
+
+def test_null_arguments_rejected(recon):
+    lib = recon.load_library()
+    assert lib.recon_default_params(64, None) == recon.RECON_EINVAL
+    assert lib.recon_query_sizes(None, None, None, None) == recon.RECON_EINVAL
+    assert lib.recon_insert_batch(None, None, None, None, 0) == recon.RECON_EINVAL
+    assert lib.recon_finalize(None, None, ctypes.c_float(0.0)) == recon.RECON_EINVAL
+    assert lib.recon_stats(None, None, None) == recon.RECON_EINVAL
+    lib.recon_destroy(None)   # ignored
+
+
+def test_init_rejects_small_workspace_without_touching_device(recon):
+    p = recon.recon_default_params(16)
+    lib = recon.load_library()
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: rejected before any device call
+    rc = lib.recon_init(ctypes.byref(p), fake, fake, fake, 16, None, ctypes.byref(ctx))
+    assert rc == recon.RECON_ENOMEM
+    assert not ctx.value
+
+
+def test_version(recon):
+    assert "gfx950" in recon.recon_version()
