@@ -1,0 +1,234 @@
+"""Benchmark of the Fourier-slice insertion path on one MI355X.
+
+A step is one pass of the whole path over the workload's slices, all inputs
+already resident in HBM: zero G and W, insert every slice in batches of
+1,500 (orientation prep, tile-binned gather, partial-sum reduction), and
+finalize (Hermitian mirror, V = G / W).  The default workload is the
+paper-scale case: 10,000 slices of 128 x 128 (half plane 128 x 65 complex64)
+into a 129^3 volume with a Kaiser-Bessel blob a = 1.9, alpha = 15, order 0
+and a 10,000-entry table.
+
+The headline value is slice-sample x voxel updates per second: the exact
+number of (disk sample, voxel within the blob) pairs of the workload, counted
+by the FP64 oracle and stored in tests/golden/pair_counts.json, divided by
+the measured time per step.  Printed as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+PEAK_HBM_GBPS = 8000.0        # MI355X HBM3E (published)
+FLOPS_PER_UPDATE = 10         # essential: 5 for d^2, 2 FMA + 1 add for G.re, G.im, W
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1910_08498_amd", "csrc", f) for f in ("kernels.hip", "slab.hip")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "insert_slab_paper_traffic.json")
+
+WORKLOAD_TEXT = {
+    "paper": "paper-scale insertion: 10,000 Fourier slices of 128x128 (half plane 128x65 complex64) "
+             "into a 129^3 complex64 G + float32 W, KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp), "
+             "batches of 1,500 slices",
+    "small": "small insertion: 500 Fourier slices of 64x64 (half plane 64x33 complex64) into a 65^3 "
+             "complex64 G + float32 W, KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp)",
+}
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def load_traffic(launch_count_per_step):
+    """HBM bytes per insertion launch from committed rocprofv3 PMC runs, if
+    they were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, n_slices: int):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    sl = workload.slices[:n_slices]
+    q = workload.quats[:n_slices]
+    oracle.insert(workload.n, sl[:8], q[:8], nthreads=threads)      # load / warm
+    t0 = time.perf_counter()
+    _, _, U = oracle.insert(workload.n, sl, q, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": U / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_slices} of {workload.S} slices of the same workload "
+                      f"({U} pairs, FP64 scatter, table lerp), {dt:.2f} s wall"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--variant", default="slab", choices=["slab", "binned", "naive"])
+    ap.add_argument("--batch", type=int, default=1500)
+    ap.add_argument("--cpu-slices", type=int, default=2500,
+                    help="slices in the CPU-oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="steps timed with the naive (plain) kernel for comparison (0 disables)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB after timing (HBM counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the insertion shards by slices, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1910_08498_amd import recon
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"bench: generating workload '{args.workload}'", file=sys.stderr, flush=True)
+    w = synth.make_workload(args.workload)
+    with open(os.path.join(ROOT, "tests", "golden", "pair_counts.json")) as f:
+        counts = json.load(f)[args.workload]
+    assert counts["n"] == w.n and counts["S"] == w.S
+    U, U_half = int(counts["U"]), int(counts["U_half"])
+
+    slices = torch.from_numpy(w.slices).to(dev)
+    quats = torch.from_numpy(w.quats).to(dev)
+    rec = recon.Reconstruction(w.n, device=dev, max_batch=args.batch)
+    variant_ids = {"slab": recon.RECON_VARIANT_SLAB, "binned": recon.RECON_VARIANT_BINNED,
+                   "naive": recon.RECON_VARIANT_NAIVE}
+    rec.set_config(variant=variant_ids[args.variant])
+    V = torch.empty_like(rec.G)
+    nb = (w.S + args.batch - 1) // args.batch
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        rec.reset()
+        for b in range(nb):
+            s0, s1 = b * args.batch, min(w.S, (b + 1) * args.batch)
+            if events is not None:
+                recon.recon_set_timing_events(rec.ctx, *events[b])
+            recon.recon_insert_batch(rec.ctx, slices[s0:s1], None, quats[s0:s1], s1 - s0)
+        if events is not None:
+            recon.recon_set_timing_events(rec.ctx, None, None)
+        rec.finalize(out=V)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nb)]
+          for _ in range(args.steps)]
+    for row in ev:                 # torch creates the HIP events on first record
+        for a, b in row:
+            a.record(stream)
+            b.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    kernel_ms = np.array([[a.elapsed_time(b) for a, b in row] for row in ev])     # [steps, nb]
+    kernel_ms_per_step = float(kernel_ms.sum(axis=1).mean())
+    avg_launch_ms = float(kernel_ms.mean())
+
+    value = U / (ms_per_step / 1e3)
+    # roofline of the dominant kernel (the insertion kernel), per launch
+    flops_per_step = FLOPS_PER_UPDATE * U_half
+    achieved_tflops = flops_per_step / (kernel_ms_per_step / 1e3) / 1e12
+    slice_bytes = w.slices.nbytes + w.quats.nbytes
+    half_vox = (w.n // 2 + 1) * (w.n + 1) ** 2
+    gw_rmw = 2 * 12 * half_vox * nb          # G (8 B) + W (4 B) read and written per launch
+    alg_bytes_step = slice_bytes + gw_rmw
+    traffic = load_traffic(nb)
+
+    plain = None
+    if args.plain_steps > 0 and args.variant != "naive":
+        rec.set_config(variant=recon.RECON_VARIANT_NAIVE)
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step()
+        torch.cuda.synchronize()
+        plain_ms = 1e3 * (time.perf_counter() - t1) / args.plain_steps
+        plain = {"value": U / (plain_ms / 1e3), "ms_per_step": plain_ms, "variant": "naive"}
+        rec.set_config(variant=variant_ids[args.variant])
+
+    if args.calib_copy_mb > 0:
+        nbytes = args.calib_copy_mb << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    if args.cpu_slices > 0:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, min(args.cpu_slices, w.S))
+
+    result = {
+        "metric": "slice-sample×voxel updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded 40-Gaussian phantom projections (exact line integrals) and their centered "
+                "DFTs, Haar-uniform orientations; stands in for EMPIAR-10010",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "n": w.n, "slices": w.S, "batch": args.batch,
+                   "variant": args.variant, "pairs_U": U, "pairs_half_box": U_half},
+        "roofline": {
+            "bound": "alu",
+            "kernel": {"slab": "k_insert_slab", "binned": "k_insert_binned", "naive": "k_insert_naive"}[args.variant],
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+            "avg_launch_ms": avg_launch_ms,
+            "launches_per_step": nb,
+            "flops_per_update": FLOPS_PER_UPDATE,
+            "hbm_alg_GBps": alg_bytes_step / (kernel_ms_per_step / 1e3) / 1e9,
+            "hbm_alg_frac": alg_bytes_step / (kernel_ms_per_step / 1e3) / 1e9 / PEAK_HBM_GBPS,
+        },
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(result), flush=True)
+    rec.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -72,9 +72,10 @@ typedef struct recon_params {
 
 /* Kernel variants of the insertion step. */
 typedef enum recon_variant {
-    RECON_VARIANT_AUTO = 0,    /* library choice (currently the binned gather) */
+    RECON_VARIANT_AUTO = 0,    /* library choice (currently the slab gather) */
     RECON_VARIANT_NAIVE = 1,   /* one thread per voxel, every slice, global reads */
-    RECON_VARIANT_BINNED = 2   /* tile-binned, LDS-staged gather (default) */
+    RECON_VARIANT_BINNED = 2,  /* 4^3 tiles binned per wavefront, lane = voxel, global reads */
+    RECON_VARIANT_SLAB = 3     /* 8^3 tiles, LDS-staged slice rectangle, slab-enumerated hits */
 } recon_variant;
 
 /* Tuning knobs of the insertion kernels (the paper's tuning-space idea,
@@ -83,7 +84,7 @@ typedef enum recon_variant {
  * "library default".  Invalid combinations are rejected with RECON_ECONFIG. */
 typedef struct recon_config {
     int32_t variant;          /* recon_variant */
-    int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8 or 16 */
+    int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8, 12 or 16 */
     int32_t group;            /* slices staged per LDS group (binned): 1..16 */
     int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 */
     int32_t split;            /* max slice-range splits of one tile (binned): 1..64 */
@@ -143,6 +144,12 @@ recon_status recon_get_config(const recon_ctx *ctx, recon_config *cfg);
 
 /* Replaces the stream used for subsequent calls. */
 recon_status recon_set_stream(recon_ctx *ctx, void *stream);
+
+/* Timing hook for measurement: when start/stop are non-NULL hipEvent_t
+ * handles, the next recon_insert_batch calls record `start` on the context's
+ * stream immediately before the main insertion kernel and `stop` immediately
+ * after it (prep and partial-sum kernels excluded).  NULL, NULL disables. */
+recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
 
 /* Slices inserted so far and slices rejected for a bad quaternion.
  * Synchronises the context's stream. */

@@ -37,7 +37,7 @@ def _load():
         ip = ctypes.POINTER(ctypes.c_int)
         up = ctypes.POINTER(ctypes.c_uint64)
         ci, cd = ctypes.c_int, ctypes.c_double
-        lib.oracle_insert.argtypes = [ci, ci, fp, dp, cd, cd, ci, ci, dp, ci, cd, dp, dp, up, ci]
+        lib.oracle_insert.argtypes = [ci, ci, fp, dp, cd, cd, ci, ci, dp, ci, cd, dp, dp, up, up, ci]
         lib.oracle_insert.restype = ci
         lib.oracle_voxels.argtypes = [ci, ci, fp, dp, cd, cd, ci, ci, dp, ci, cd, ci, ip, dp, dp, up, ci]
         lib.oracle_voxels.restype = ci
@@ -90,9 +90,10 @@ def _prep(n, slices, quats):
     return n, S, slices, R
 
 
-def insert(n, slices, quats, blob: Blob = Blob(), r_max=None, nthreads=None):
+def insert(n, slices, quats, blob: Blob = Blob(), r_max=None, nthreads=None, with_half=False):
     """Scatter all slices into the full box.  Returns (G complex128 [(n+1)]^3,
-    W float64 [(n+1)]^3, U = number of (sample, voxel) pairs within the blob)."""
+    W float64 [(n+1)]^3, U = number of (sample, voxel) pairs within the blob);
+    with_half=True appends the number of those pairs whose voxel has x >= 0."""
     lib = _load()
     n, S, slices, R = _prep(n, slices, quats)
     r_max = 0.5 * n if r_max is None else float(r_max)
@@ -100,16 +101,18 @@ def insert(n, slices, quats, blob: Blob = Blob(), r_max=None, nthreads=None):
     G = np.zeros((dim, dim, dim, 2), dtype=np.float64)
     W = np.zeros((dim, dim, dim), dtype=np.float64)
     U = ctypes.c_uint64(0)
+    Uh = ctypes.c_uint64(0)
     table = blob.table()
     nthreads = nthreads or min(8, os.cpu_count() or 1)
     fl = slices.view(np.float32)
     rc = lib.oracle_insert(n, S, _ptr(fl, ctypes.c_float), _ptr(R, ctypes.c_double),
                            blob.a, blob.alpha, blob.m, blob.mode, _ptr(table, ctypes.c_double),
                            int(blob.N), r_max, _ptr(G, ctypes.c_double), _ptr(W, ctypes.c_double),
-                           ctypes.byref(U), int(nthreads))
+                           ctypes.byref(U), ctypes.byref(Uh), int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_insert failed ({rc})")
-    return G[..., 0] + 1j * G[..., 1], W, int(U.value)
+    out = (G[..., 0] + 1j * G[..., 1], W, int(U.value))
+    return out + (int(Uh.value),) if with_half else out
 
 
 def voxels(n, slices, quats, vox, blob: Blob = Blob(), r_max=None, nthreads=None):

@@ -106,11 +106,12 @@ static void sample_full(const float *Fs, int n, int kx, int ky, double *re, doub
 /* Scatter every sample of every slice into the full box.
  *   F : [S][n][n/2+1] complex64 (interleaved float pairs)
  *   R : [S][3][3] row-major FP64 rotation matrices
- *   G : [(n+1)^3][2] FP64 (accumulated into), W : [(n+1)^3] FP64, U : pair count
+ *   G : [(n+1)^3][2] FP64 (accumulated into), W : [(n+1)^3] FP64, U : pair count,
+ *   Uhalf (may be NULL) : pairs whose voxel has x >= 0
  * Returns 0, or -1 on invalid arguments, -2 when memory runs out. */
 int oracle_insert(int n, int S, const float *F, const double *R,
                   double a, double alpha, int m, int mode, const double *table, int N,
-                  double r_max, double *G, double *W, uint64_t *U, int nthreads)
+                  double r_max, double *G, double *W, uint64_t *U, uint64_t *Uhalf, int nthreads)
 {
     blob_t b;
     if (n < 2 || (n & 1) || S < 0 || !G || !W || !U) return -1;
@@ -128,7 +129,8 @@ int oracle_insert(int n, int S, const float *F, const double *R,
     double **pg = calloc((size_t)nthreads, sizeof(double *));
     double **pw = calloc((size_t)nthreads, sizeof(double *));
     uint64_t *pu = calloc((size_t)nthreads, sizeof(uint64_t));
-    int oom = (!pg || !pw || !pu);
+    uint64_t *ph = calloc((size_t)nthreads, sizeof(uint64_t));
+    int oom = (!pg || !pw || !pu || !ph);
     for (int t = 0; t < nthreads && !oom; ++t) {
         pg[t] = calloc(nvox * 2, sizeof(double));
         pw[t] = calloc(nvox, sizeof(double));
@@ -144,7 +146,7 @@ int oracle_insert(int n, int S, const float *F, const double *R,
             tid = omp_get_thread_num();
 #endif
             double *g = pg[tid], *wv = pw[tid];
-            uint64_t cnt = 0;
+            uint64_t cnt = 0, cnt_half = 0;
             const float *Fs = F + (size_t)s * slice_len;
             const double *Rs = R + (size_t)s * 9;
             for (int ky = -h; ky <= h; ++ky) {
@@ -173,6 +175,7 @@ int oracle_insert(int n, int S, const float *F, const double *R,
                                 g[2 * idx + 1] += wgt * fim;
                                 wv[idx] += wgt;
                                 ++cnt;
+                                if (vx >= 0) ++cnt_half;
                             }
                         }
                     }
@@ -182,6 +185,7 @@ int oracle_insert(int n, int S, const float *F, const double *R,
 #pragma omp atomic
 #endif
             pu[tid] += cnt;
+            ph[tid] += cnt_half;
         }
         for (int t = 0; t < nthreads; ++t) {
             for (size_t i = 0; i < nvox; ++i) {
@@ -190,10 +194,11 @@ int oracle_insert(int n, int S, const float *F, const double *R,
                 W[i] += pw[t][i];
             }
             *U += pu[t];
+            if (Uhalf) *Uhalf += ph[t];
         }
     }
     for (int t = 0; t < nthreads && pg && pw; ++t) { free(pg[t]); free(pw[t]); }
-    free(pg); free(pw); free(pu);
+    free(pg); free(pw); free(pu); free(ph);
     return oom ? -2 : 0;
 }
 

@@ -59,6 +59,14 @@ hipError_t launch_insert_binned(const Geom &g, bool lerp, const float2 *slices,
 hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   const float4 *partials, float2 *G, float *W,
                                   hipStream_t st);
+// Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
+size_t slab_lds_bytes(const Geom &g, int waves_per_block);
+hipError_t launch_insert_slab(const Geom &g, bool lerp, const float2 *slices, const Orient *orient,
+                              int count, const float2 *table, const Item *items, int nitems,
+                              float4 *partials, int inner_chunk, int blocks, int waves_per_block,
+                              Counters *ctr, float2 *G, float *W, hipStream_t st);
+hipError_t launch_reduce_partials8(const Geom &g, const Item *items, int nitems,
+                                   const float4 *partials, float2 *G, float *W, hipStream_t st);
 hipError_t launch_finalize(const Geom &g, float2 *G, float *W, float2 *V, float thr,
                            hipStream_t st);
 

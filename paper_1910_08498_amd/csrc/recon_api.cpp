@@ -104,35 +104,39 @@ struct Plan {
     int nslots = 0;
 };
 
-// Tiles of 4x4x4 voxels over the half box x in [0, h], y, z in [-h, h].
-// A tile at centre distance r sees, for uniformly distributed slice normals,
-// about min(1, (a + 2.6) / r) of the slices; tiles whose every voxel is out
-// of reach of the disk |k| < r_max are dropped.  Heavy tiles are split into
-// up to `split` slice ranges so that no item costs much more than `target`
-// slice visits; items are ordered by decreasing estimated cost.
-Plan make_plan(const recon_params &p, int split)
+// Tiles of E x E x E voxels (E = 4 or 8) over the half box x in [0, h],
+// y, z in [-h, h].  A tile at centre distance r sees, for uniformly
+// distributed slice normals, about min(1, (a + ext) / r) of the slices
+// (ext = half the tile diagonal); tiles whose every voxel is out of reach of
+// the disk |k| < r_max are dropped.  Heavy tiles are split into up to `split`
+// slice ranges so that no item costs much more than `target` slice visits;
+// items are ordered by decreasing estimated cost.
+Plan make_plan(const recon_params &p, int split, int E)
 {
     Plan plan;
     const int h = p.n / 2, dim = p.n + 1;
-    const int TX = (h + 1 + 3) / 4, TY = (dim + 3) / 4, TZ = TY;
-    const double a = p.blob_radius, reach = p.r_max + a + 2.6;
+    const int TX = (h + 1 + E - 1) / E, TY = (dim + E - 1) / E, TZ = TY;
+    const double half = 0.5 * (E - 1);
+    const double ext = half * std::sqrt(3.0);
+    const double a = p.blob_radius, reach = p.r_max + a + ext + 0.1;
     struct Est { int tile; double cost; };
     std::vector<Est> tiles;
     double total = 0.0;
     for (int tz = 0; tz < TZ; ++tz)
         for (int ty = 0; ty < TY; ++ty)
             for (int tx = 0; tx < TX; ++tx) {
-                const double cx = 4.0 * tx + 1.5, cy = 4.0 * ty + 1.5 - h, cz = 4.0 * tz + 1.5 - h;
+                const double cx = E * tx + half, cy = E * ty + half - h, cz = E * tz + half - h;
                 const double r = std::sqrt(cx * cx + cy * cy + cz * cz);
                 if (r > reach) continue;
-                const double frac = std::min(1.0, (a + 2.6) / std::max(r, 1e-9));
+                const double frac = std::min(1.0, (a + ext) / std::max(r, 1e-9));
                 const double cost = frac * p.max_batch;
                 tiles.push_back({tx + TX * (ty + TY * tz), cost});
                 total += cost;
             }
-    // target item cost: 1/8 of the mean cost per wave slot of a 256-CU device
-    // running 16 waves per CU, but never below 48 slice visits
-    const double target = std::max(48.0, total / (256.0 * 16.0 * 8.0));
+    // target item cost: a quarter of the mean cost per wavefront slot of a
+    // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits
+    const double slots = 256.0 * (E == 4 ? 16.0 : 8.0);
+    const double target = std::max(24.0, total / (slots * 4.0));
     struct Tmp { Item it; double cost; };
     std::vector<Tmp> tmp;
     for (const Est &e : tiles) {
@@ -149,13 +153,15 @@ Plan make_plan(const recon_params &p, int split)
     return plan;
 }
 
+int tile_edge(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 4; }
+
 constexpr int kMaxSplit = 64;
 
 struct Layout {
     size_t ctr = 0, table = 0, orient = 0, items = 0, partials = 0, total = 0;
 };
 
-Layout layout_for(const recon_params &p, int nitems, int nslots)
+Layout layout_for(const recon_params &p, int nitems, size_t partial_vox)
 {
     Layout L;
     size_t off = 0;
@@ -168,22 +174,33 @@ Layout layout_for(const recon_params &p, int nitems, int nslots)
     L.items = off;
     off = align_up(off + static_cast<size_t>(nitems) * sizeof(Item), 256);
     L.partials = off;
-    off = align_up(off + static_cast<size_t>(nslots) * 64 * sizeof(float4), 256);
+    off = align_up(off + partial_vox * sizeof(float4), 256);
     L.total = off;
     return L;
+}
+
+// Workspace layout large enough for the plan of every variant at the largest split.
+Layout worst_layout(const recon_params &p)
+{
+    Plan p4 = make_plan(p, kMaxSplit, 4), p8 = make_plan(p, kMaxSplit, 8);
+    const int nitems = static_cast<int>(std::max(p4.items.size(), p8.items.size()));
+    const size_t pv = std::max(static_cast<size_t>(p4.nslots) * 64, static_cast<size_t>(p8.nslots) * 512);
+    return layout_for(p, nitems, pv);
 }
 
 recon_config default_config()
 {
     recon_config c;
     std::memset(&c, 0, sizeof(c));
-    c.variant = RECON_VARIANT_BINNED;
-    c.waves_per_block = 16;
+    c.variant = RECON_VARIANT_SLAB;
+    c.waves_per_block = 8;
     c.group = 1;
     c.inner_chunk = 32;
-    c.split = 16;
+    c.split = 32;
     return c;
 }
+
+int default_waves(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 16; }
 
 }  // namespace
 
@@ -202,6 +219,8 @@ struct recon_ctx {
     int num_cu;
     size_t max_lds;
     int max_threads;
+    hipEvent_t ev_start;  // optional timing events around the insertion kernel
+    hipEvent_t ev_stop;
 };
 
 extern "C" {
@@ -233,10 +252,7 @@ recon_status recon_query_sizes(const recon_params *p, size_t *g_bytes, size_t *w
     const size_t nvox = dim * dim * dim;
     if (g_bytes) *g_bytes = nvox * sizeof(float2);
     if (w_bytes) *w_bytes = nvox * sizeof(float);
-    if (ws_bytes) {
-        Plan worst = make_plan(*p, kMaxSplit);
-        *ws_bytes = layout_for(*p, static_cast<int>(worst.items.size()), worst.nslots).total;
-    }
+    if (ws_bytes) *ws_bytes = worst_layout(*p).total;
     return RECON_OK;
 }
 
@@ -285,8 +301,6 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
     c->max_threads = prop.maxThreadsPerBlock;
-    if (static_cast<size_t>(p->table_size) * sizeof(float2) > c->max_lds)
-        c->cfg.variant = RECON_VARIANT_NAIVE;   // table cannot be staged in LDS
 
     const int h = p->n / 2;
     c->g.n = p->n;
@@ -299,10 +313,15 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->g.tscale = static_cast<float>((p->table_size - 1) /
                                      (static_cast<double>(p->blob_radius) * p->blob_radius));
     c->g.r2max = p->r_max * p->r_max;
+    if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
+        // blob table too large for the slab kernel's LDS budget
+        c->cfg.variant = static_cast<size_t>(p->table_size) * sizeof(float2) <= c->max_lds ? RECON_VARIANT_BINNED
+                                                                                             : RECON_VARIANT_NAIVE;
+        c->cfg.waves_per_block = 16;
+    }
 
-    Plan worst = make_plan(*p, kMaxSplit);
-    c->L = layout_for(*p, static_cast<int>(worst.items.size()), worst.nslots);
-    c->plan = make_plan(*p, c->cfg.split);
+    c->L = worst_layout(*p);
+    c->plan = make_plan(*p, c->cfg.split, tile_edge(c->cfg.variant));
 
     // blob table: entry i = (T[i], T[i+1] - T[i]), T[i] = b(i a^2 / (N-1)), built in FP64
     const int N = p->table_size;
@@ -362,22 +381,41 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     const float2 *slices = static_cast<const float2 *>(d_slices);
     hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
+    if (c->ev_start) {
+        e = hipEventRecord(c->ev_start, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "record start event");
+    }
     if (c->cfg.variant == RECON_VARIANT_NAIVE) {
         e = recon::launch_insert_naive(c->g, c->p.table_lerp != 0, slices, orient, count, table,
                                        c->cfg.inner_chunk, c->cfg.waves_per_block, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "naive insert kernel launch");
+        if (c->ev_stop) {
+            e = hipEventRecord(c->ev_stop, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "record stop event");
+        }
         return RECON_OK;
     }
     const Item *items = reinterpret_cast<const Item *>(c->ws + c->L.items);
     float4 *partials = reinterpret_cast<float4 *>(c->ws + c->L.partials);
     const int nitems = static_cast<int>(c->plan.items.size());
     const int blocks = c->num_cu;
-    e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
-                                    partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
-                                    c->W, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "binned insert kernel launch");
+    const bool slab = c->cfg.variant == RECON_VARIANT_SLAB;
+    if (slab)
+        e = recon::launch_insert_slab(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
+                                      partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G, c->W,
+                                      c->stream);
+    else
+        e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
+                                        partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
+                                        c->W, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "insert kernel launch");
+    if (c->ev_stop) {
+        e = hipEventRecord(c->ev_stop, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "record stop event");
+    }
     if (c->plan.nslots > 0) {
-        e = recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
+        e = slab ? recon::launch_reduce_partials8(c->g, items, nitems, partials, c->G, c->W, c->stream)
+                 : recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
     }
     return RECON_OK;
@@ -400,15 +438,15 @@ recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
     recon_config d = default_config();
     recon_config n = cfg ? *cfg : d;
     if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
-    if (n.waves_per_block == 0) n.waves_per_block = d.waves_per_block;
+    if (n.waves_per_block == 0) n.waves_per_block = default_waves(n.variant);
     if (n.group == 0) n.group = d.group;
     if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
     if (n.split == 0) n.split = d.split;
-    if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED)
+    if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED && n.variant != RECON_VARIANT_SLAB)
         return fail(RECON_ECONFIG, "unknown variant %d", n.variant);
     const int wpb = n.waves_per_block;
-    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16)
-        return fail(RECON_ECONFIG, "waves_per_block must be 1, 2, 4, 8 or 16");
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 12 && wpb != 16)
+        return fail(RECON_ECONFIG, "waves_per_block must be 1, 2, 4, 8, 12 or 16");
     if (64 * wpb > c->max_threads) return fail(RECON_ECONFIG, "work-group of %d threads exceeds device", 64 * wpb);
     if (n.group < 1 || n.group > 16) return fail(RECON_ECONFIG, "group must be in [1, 16]");
     if (n.inner_chunk < 1 || n.inner_chunk > 256) return fail(RECON_ECONFIG, "inner_chunk must be in [1, 256]");
@@ -416,10 +454,13 @@ recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
     if (n.variant == RECON_VARIANT_BINNED &&
         static_cast<size_t>(c->p.table_size) * sizeof(float2) > c->max_lds)
         return fail(RECON_ECONFIG, "blob table of %d entries does not fit in LDS", c->p.table_size);
-    const bool replan = n.split != c->cfg.split;
+    if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, wpb) > c->max_lds)
+        return fail(RECON_ECONFIG, "slab kernel needs %zu bytes of LDS with %d waves (device: %zu)",
+                    recon::slab_lds_bytes(c->g, wpb), wpb, c->max_lds);
+    const bool replan = n.split != c->cfg.split || tile_edge(n.variant) != tile_edge(c->cfg.variant);
     c->cfg = n;
     if (replan) {
-        c->plan = make_plan(c->p, n.split);
+        c->plan = make_plan(c->p, n.split, tile_edge(n.variant));
         return upload_plan(c);
     }
     return RECON_OK;
@@ -436,6 +477,15 @@ recon_status recon_set_stream(recon_ctx *c, void *stream)
 {
     if (!c) return fail(RECON_EINVAL, "ctx is NULL");
     c->stream = static_cast<hipStream_t>(stream);
+    return RECON_OK;
+}
+
+recon_status recon_set_timing_events(recon_ctx *c, void *start, void *stop)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    if ((start == nullptr) != (stop == nullptr)) return fail(RECON_EINVAL, "give both events or neither");
+    c->ev_start = static_cast<hipEvent_t>(start);
+    c->ev_stop = static_cast<hipEvent_t>(stop);
     return RECON_OK;
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librecon.so")
 
 RECON_OK, RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ECONFIG = 0, -1, -2, -3, -4
 RECON_SLICE_C64, RECON_SLICE_F16, RECON_SLICE_BF16 = 0, 1, 2
-RECON_VARIANT_AUTO, RECON_VARIANT_NAIVE, RECON_VARIANT_BINNED = 0, 1, 2
+RECON_VARIANT_AUTO, RECON_VARIANT_NAIVE, RECON_VARIANT_BINNED, RECON_VARIANT_SLAB = 0, 1, 2, 3
 
 
 class recon_params(ctypes.Structure):
@@ -63,6 +63,7 @@ def load_library():
         "recon_set_config": ([vp, P(recon_config)], i32),
         "recon_get_config": ([vp, P(recon_config)], i32),
         "recon_set_stream": ([vp, vp], i32),
+        "recon_set_timing_events": ([vp, vp, vp], i32),
         "recon_stats": ([vp, P(ctypes.c_uint64), P(ctypes.c_uint64)], i32),
         "recon_destroy": ([vp], None),
         "recon_last_error": ([], ctypes.c_char_p),
@@ -137,6 +138,13 @@ def recon_get_config(ctx) -> recon_config:
 
 def recon_set_stream(ctx, stream=None):
     _check(load_library().recon_set_stream(ctx, _stream(stream)))
+
+
+def recon_set_timing_events(ctx, start=None, stop=None):
+    """start/stop: torch.cuda.Event objects (or None to disable)."""
+    sp = None if start is None else ctypes.c_void_p(start.cuda_event)
+    tp = None if stop is None else ctypes.c_void_p(stop.cuda_event)
+    _check(load_library().recon_set_timing_events(ctx, sp, tp))
 
 
 def recon_stats(ctx):

@@ -30,14 +30,19 @@ def recon(torch_dev):
     return r
 
 
-VARIANTS = ["naive", "binned"]
+VARIANTS = ["naive", "binned", "slab"]
 
 
-def gpu_run(recon, torch_dev, n, slices, quats, variant="binned", finalize=True, **params):
+def variant_id(recon, variant):
+    return {"naive": recon.RECON_VARIANT_NAIVE, "binned": recon.RECON_VARIANT_BINNED,
+            "slab": recon.RECON_VARIANT_SLAB}[variant]
+
+
+def gpu_run(recon, torch_dev, n, slices, quats, variant="slab", finalize=True, **params):
     torch, dev = torch_dev
     print(f"[gpu] n={n} S={len(quats)} variant={variant} params={params}", flush=True)
     rec = recon.Reconstruction(n, device=dev, **params)
-    rec.set_config(variant=recon.RECON_VARIANT_NAIVE if variant == "naive" else recon.RECON_VARIANT_BINNED)
+    rec.set_config(variant=variant_id(recon, variant))
     rec.insert(torch.from_numpy(np.ascontiguousarray(slices)).to(dev),
                torch.from_numpy(np.ascontiguousarray(quats)).to(dev))
     V = rec.finalize() if finalize else None
@@ -129,10 +134,11 @@ def test_rejected_orientations_contribute_nothing(recon, torch_dev, variant):
     assert gpu[3] == (w.S, len(bad))
 
 
-def test_binned_is_bitwise_deterministic(recon, torch_dev, small):
+@pytest.mark.parametrize("variant", ["binned", "slab"])
+def test_queue_variants_are_bitwise_deterministic(recon, torch_dev, small, variant):
     w, _ = small
-    a = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, "binned")
-    b = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, "binned")
+    a = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)
+    b = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)
     assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
     assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
 
@@ -197,7 +203,7 @@ def paper_scale():
     return synth.make_workload("paper")
 
 
-@pytest.mark.parametrize("variant", ["binned"])
+@pytest.mark.parametrize("variant", ["binned", "slab"])
 def test_paper_scale_sampled_voxels(recon, torch_dev, paper_scale, variant):
     w = paper_scale
     G, W, V, stats = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)
