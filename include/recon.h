@@ -87,8 +87,11 @@ typedef struct recon_config {
     int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8, 12 or 16 */
     int32_t group;            /* slices staged per LDS group (binned): 1..16 */
     int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 */
-    int32_t split;            /* max slice-range splits of one tile (binned): 1..64 */
-    int32_t reserved[11];
+    int32_t split;            /* max slice-range splits of one tile (binned, slab): 1..64 */
+    int32_t slab_flags;       /* slab variant, 4 | bits: bit 0 LDS float atomics for the
+                                 accumulators, bit 1 issue all window reads before use
+                                 (default 4 | 2) */
+    int32_t reserved[10];
 } recon_config;
 
 typedef struct recon_ctx recon_ctx;
@@ -150,6 +153,60 @@ recon_status recon_set_stream(recon_ctx *ctx, void *stream);
  * stream immediately before the main insertion kernel and `stop` immediately
  * after it (prep and partial-sum kernels excluded).  NULL, NULL disables. */
 recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
+
+/* ---------------------------------------------------------------------
+ * Dynamic autotuning (Sect. 3.2, "Offline and Dynamic tuning", and its use
+ * in Sect. 5.3: non-blocking tuning, where every tuning step performs real
+ * work with a new configuration, here one recon_insert_batch call, and the
+ * search continues with the fastest configuration once it stops).
+ * The tuning space is the set of kernel configurations (recon_config) that
+ * are runnable on the context's device.
+ * --------------------------------------------------------------------- */
+typedef struct recon_tune_opts {
+    int32_t max_steps;          /* configurations to try; 0 = the whole space */
+    int32_t reserved0;
+    uint64_t seed;              /* seed of the random search order */
+    double target_ns_per_slice; /* stop early once a configuration reaches this
+                                   insertion-kernel time per slice (0 = never) */
+    int32_t reserved[8];
+} recon_tune_opts;
+
+typedef struct recon_tune_info {
+    int32_t active;             /* 1 while steps remain */
+    int32_t steps_done;         /* configurations measured so far */
+    int32_t space_size;         /* configurations in the tuning space */
+    int32_t best_index;         /* index of the fastest measured (-1 if none) */
+    double best_ns_per_slice;   /* its insertion-kernel time per slice */
+    double mean_ns_per_slice;   /* mean over the measured configurations */
+    recon_config best;          /* the fastest measured configuration */
+} recon_tune_info;
+
+/* Number of configurations in the tuning space, and the index-th of them
+ * (in a fixed enumeration order). */
+recon_status recon_tune_space_size(const recon_ctx *ctx, int32_t *size);
+recon_status recon_tune_space_config(const recon_ctx *ctx, int32_t index, recon_config *out);
+
+/* Starts a random search: the next recon_insert_batch calls each run one
+ * untried configuration, timed with events around the insertion kernel.
+ * Measuring a step waits for the previous step's kernel (tuning steps are
+ * not overlapped, as in the paper's tuning phase).  After max_steps steps, or
+ * when the target is met, the fastest configuration is selected and kept. */
+recon_status recon_tune_begin(recon_ctx *ctx, const recon_tune_opts *opts);
+
+/* Progress of the search (waits for a pending step's timing). */
+recon_status recon_tune_get_info(recon_ctx *ctx, recon_tune_info *info);
+
+/* Ends the search now and selects the fastest measured configuration. */
+recon_status recon_tune_end(recon_ctx *ctx);
+
+/* Amortization of dynamic tuning (Sect. 5.4).  Eq. 4: kernel invocations
+ * n needed so that s tuning steps at average time t_avg, followed by
+ * invocations at t_well, run at relative performance rp of always running
+ * at t_well: n = rp s (t_avg / t_well - 1) / (1 - rp), for 0 < rp < 1.
+ * Eq. 5: random-search steps s that find one of a fraction r of
+ * well-performing configurations with probability p: s = log(1-p) / log(1-r). */
+recon_status recon_tune_invocations(double rp, double s, double t_avg, double t_well, double *n);
+recon_status recon_tune_steps(double r, double p, double *s);
 
 /* Slices inserted so far and slices rejected for a bad quaternion.
  * Synchronises the context's stream. */

@@ -33,20 +33,28 @@ __device__ __forceinline__ float blob_lookup(const float2 *__restrict__ tab, flo
 }
 
 // Full-plane sample F~(k) from the stored half plane of one slice.
-__device__ __forceinline__ float2 fetch_full(const float2 *__restrict__ Fs, const Geom &g,
+__device__ __forceinline__ float2 fetch_full(const unsigned char *__restrict__ Fs, float scale, const Geom &g,
                                              int kx, int ky)
 {
     const bool direct = kx > 0 || (kx == 0 && ky >= 0);
     const int row = direct ? ky + g.h : g.h - ky;
     const int col = direct ? kx : -kx;
-    float2 f = Fs[row * g.sw + col];
+    float2 f = decode_sample(Fs, row * g.sw + col, g.dtype, scale);
     if (!direct) f.y = -f.y;
     return f;
 }
 
+// Start of slice s in a batch of stored slices, and its scale.
+__device__ __forceinline__ const unsigned char *slice_base(const void *slices, int s, const Geom &g)
+{
+    return static_cast<const unsigned char *>(slices) +
+           static_cast<size_t>(s) * static_cast<size_t>(g.n) * g.sw * sample_bytes(g.dtype);
+}
+__device__ __forceinline__ float slice_scale(int s, const Geom &g) { return g.scales ? g.scales[s] : 1.0f; }
+
 // Accumulates the WIN x WIN window of one (voxel, slice) pair.
 template <int WIN, bool LERP>
-__device__ __forceinline__ void window_global(const float2 *__restrict__ Fs, const Geom &g,
+__device__ __forceinline__ void window_global(const unsigned char *__restrict__ Fs, float scale, const Geom &g,
                                               const float2 *__restrict__ tab, float ux, float uy,
                                               float uz, float &pr, float &pi, float &pw)
 {
@@ -66,7 +74,7 @@ __device__ __forceinline__ void window_global(const float2 *__restrict__ Fs, con
             const bool in_disk = static_cast<float>(kx * kx + ky * ky) < g.r2max;
             if (d2 <= g.a2 && in_disk) {
                 const float w = blob_lookup<LERP>(tab, d2 * g.tscale, g.N);
-                const float2 f = fetch_full(Fs, g, kx, ky);
+                const float2 f = fetch_full(Fs, scale, g, kx, ky);
                 pr = fmaf(w, f.x, pr);
                 pi = fmaf(w, f.y, pi);
                 pw += w;
@@ -141,7 +149,7 @@ hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *
 // naive gather: one thread per voxel of the half box, every slice
 // ---------------------------------------------------------------------------
 template <int WIN, bool LERP>
-__global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const float2 *__restrict__ slices,
+__global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const void *__restrict__ slices,
                                                        const Orient *__restrict__ orient, int count,
                                                        const float2 *__restrict__ tab, int inner_chunk,
                                                        float2 *__restrict__ G, float *__restrict__ W)
@@ -157,7 +165,6 @@ __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const float2 *__r
     const float vx = static_cast<float>(ix);
     const float vy = static_cast<float>(iy - g.h);
     const float vz = static_cast<float>(iz - g.h);
-    const size_t slen = static_cast<size_t>(g.n) * g.sw;
 
     float ore = 0.f, oim = 0.f, ow = 0.f;
     float ire = 0.f, iim = 0.f, iw = 0.f;
@@ -169,7 +176,8 @@ __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const float2 *__r
         if (fabsf(uz) <= g.a) {
             const float ux = fmaf(o.e1.x, vx, fmaf(o.e1.y, vy, o.e1.z * vz));
             const float uy = fmaf(o.e2.x, vx, fmaf(o.e2.y, vy, o.e2.z * vz));
-            window_global<WIN, LERP>(slices + s * slen, g, tab, ux, uy, uz, ire, iim, iw);
+            window_global<WIN, LERP>(slice_base(slices, s, g), slice_scale(s, g), g, tab, ux, uy, uz, ire, iim,
+                                     iw);
         }
         if (++inner == inner_chunk) {
             ore += ire; oim += iim; ow += iw;
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const float2 *__r
 }
 
 template <int WIN, bool LERP>
-static hipError_t launch_naive_t(const Geom &g, const float2 *slices, const Orient *orient, int count,
+static hipError_t launch_naive_t(const Geom &g, const void *slices, const Orient *orient, int count,
                                  const float2 *tab, int inner_chunk, int wpb, float2 *G, float *W,
                                  hipStream_t st)
 {
@@ -212,7 +220,7 @@ static hipError_t launch_naive_t(const Geom &g, const float2 *slices, const Orie
 
 static inline int window_size(float a) { return static_cast<int>(floorf(2.0f * a)) + 1; }
 
-hipError_t launch_insert_naive(const Geom &g, bool lerp, const float2 *slices, const Orient *orient,
+hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices, const Orient *orient,
                                int count, const float2 *table, int inner_chunk, int waves_per_block,
                                float2 *G, float *W, hipStream_t st)
 {
@@ -229,7 +237,7 @@ hipError_t launch_insert_naive(const Geom &g, bool lerp, const float2 *slices, c
 // ---------------------------------------------------------------------------
 template <int WIN, bool LERP>
 __global__ __launch_bounds__(1024) void k_insert_binned(
-    Geom g, const float2 *__restrict__ slices, const Orient *__restrict__ orient, int count,
+    Geom g, const void *__restrict__ slices, const Orient *__restrict__ orient, int count,
     const float2 *__restrict__ table_g, const Item *__restrict__ items, int nitems,
     float4 *__restrict__ partials, int inner_chunk, Counters *__restrict__ ctr,
     float2 *__restrict__ G, float *__restrict__ W)
@@ -241,7 +249,6 @@ __global__ __launch_bounds__(1024) void k_insert_binned(
     const int lane = threadIdx.x & 63;
     const int TX = (g.h + 1 + 3) >> 2;
     const int TY = (g.dim + 3) >> 2;
-    const size_t slen = static_cast<size_t>(g.n) * g.sw;
     // conservative in-plane reach of a tile: r_max + a + 1.5 * sqrt(6)
     const float reach = sqrtf(g.r2max) + g.a + 3.675f;
     const float reach2 = reach * reach;
@@ -294,7 +301,8 @@ __global__ __launch_bounds__(1024) void k_insert_binned(
                 if (in_box && fabsf(uz) <= g.a) {
                     const float ux = fmaf(o.e1.x, vx, fmaf(o.e1.y, vy, o.e1.z * vz));
                     const float uy = fmaf(o.e2.x, vx, fmaf(o.e2.y, vy, o.e2.z * vz));
-                    window_global<WIN, LERP>(slices + ss * slen, g, tab, ux, uy, uz, ire, iim, iw);
+                    window_global<WIN, LERP>(slice_base(slices, ss, g), slice_scale(ss, g), g, tab, ux, uy, uz, ire,
+                                             iim, iw);
                 }
                 if (++inner == inner_chunk) {
                     ore += ire; oim += iim; ow += iw;
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_insert_binned(
 }
 
 template <int WIN, bool LERP>
-static hipError_t launch_binned_t(const Geom &g, const float2 *slices, const Orient *orient, int count,
+static hipError_t launch_binned_t(const Geom &g, const void *slices, const Orient *orient, int count,
                                   const float2 *table, const Item *items, int nitems, float4 *partials,
                                   int inner_chunk, int blocks, int wpb, Counters *ctr, float2 *G,
                                   float *W, hipStream_t st)
@@ -331,7 +339,7 @@ static hipError_t launch_binned_t(const Geom &g, const float2 *slices, const Ori
     return hipGetLastError();
 }
 
-hipError_t launch_insert_binned(const Geom &g, bool lerp, const float2 *slices, const Orient *orient,
+hipError_t launch_insert_binned(const Geom &g, bool lerp, const void *slices, const Orient *orient,
                                 int count, const float2 *table, const Item *items, int nitems,
                                 float4 *partials, int inner_chunk, int blocks, int waves_per_block,
                                 Counters *ctr, float2 *G, float *W, hipStream_t st)

@@ -18,7 +18,27 @@ struct Geom {
     float tscale;   // (N - 1) / a^2 : table index per unit squared distance
     int N;          // table entries
     float r2max;    // r_max^2 : samples with kx^2 + ky^2 < r2max are inserted
+    int dtype;      // slice storage: 0 complex64, 1 half pairs x per-slice scale, 2 bfloat16 pairs
+    const float *scales;  // per-slice scales of the current batch (half storage), else NULL
 };
+
+// Bytes per stored sample for a storage type.
+__host__ __device__ inline int sample_bytes(int dtype) { return dtype == 0 ? 8 : 4; }
+
+// Decodes one stored sample (element index idx of the slice starting at
+// `base`); `scale` multiplies half-precision samples.
+__device__ __forceinline__ float2 decode_sample(const unsigned char *__restrict__ base, int idx, int dtype,
+                                                float scale)
+{
+    if (dtype == 0) return reinterpret_cast<const float2 *>(base)[idx];
+    const unsigned raw = reinterpret_cast<const unsigned *>(base)[idx];
+    if (dtype == 1) {
+        const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
+        const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
+        return make_float2(static_cast<float>(lo) * scale, static_cast<float>(hi) * scale);
+    }
+    return make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
+}
 
 // Per-slice orientation record written by the prep kernel (64 bytes).
 // e1, e2 are the images of the slice's x and y axes in the volume, e3 the
@@ -47,11 +67,11 @@ struct Item {
 hipError_t launch_zero(float *p, size_t count, hipStream_t st);
 hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr,
                        hipStream_t st);
-hipError_t launch_insert_naive(const Geom &g, bool lerp, const float2 *slices,
+hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices,
                                const Orient *orient, int count, const float2 *table,
                                int inner_chunk, int waves_per_block, float2 *G, float *W,
                                hipStream_t st);
-hipError_t launch_insert_binned(const Geom &g, bool lerp, const float2 *slices,
+hipError_t launch_insert_binned(const Geom &g, bool lerp, const void *slices,
                                 const Orient *orient, int count, const float2 *table,
                                 const Item *items, int nitems, float4 *partials,
                                 int inner_chunk, int blocks, int waves_per_block,
@@ -61,7 +81,7 @@ hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   hipStream_t st);
 // Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
 size_t slab_lds_bytes(const Geom &g, int waves_per_block);
-hipError_t launch_insert_slab(const Geom &g, bool lerp, const float2 *slices, const Orient *orient,
+hipError_t launch_insert_slab(const Geom &g, bool lerp, int flags, const void *slices, const Orient *orient,
                               int count, const float2 *table, const Item *items, int nitems,
                               float4 *partials, int inner_chunk, int blocks, int waves_per_block,
                               Counters *ctr, float2 *G, float *W, hipStream_t st);

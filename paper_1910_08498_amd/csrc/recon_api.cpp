@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -89,8 +90,9 @@ recon_status validate(const recon_params *p)
         return fail(RECON_EINVAL, "table_lerp must be 0 or 1");
     if (!(p->r_max > 0.0f) || p->r_max > 0.5f * p->n)
         return fail(RECON_EINVAL, "r_max must be in (0, n/2] (got %g)", p->r_max);
-    if (p->slice_dtype != RECON_SLICE_C64)
-        return fail(RECON_EINVAL, "slice_dtype %d is not supported by this build", p->slice_dtype);
+    if (p->slice_dtype != RECON_SLICE_C64 && p->slice_dtype != RECON_SLICE_F16 && p->slice_dtype != RECON_SLICE_BF16)
+        return fail(RECON_EINVAL, "slice_dtype must be 0 (complex64), 1 (half) or 2 (bfloat16) (got %d)",
+                    p->slice_dtype);
     if (p->max_batch < 1 || p->max_batch > (1 << 24))
         return fail(RECON_EINVAL, "max_batch must be in [1, 2^24] (got %d)", p->max_batch);
     return RECON_OK;
@@ -116,20 +118,27 @@ Plan make_plan(const recon_params &p, int split, int E)
     Plan plan;
     const int h = p.n / 2, dim = p.n + 1;
     const int TX = (h + 1 + E - 1) / E, TY = (dim + E - 1) / E, TZ = TY;
-    const double half = 0.5 * (E - 1);
-    const double ext = half * std::sqrt(3.0);
-    const double a = p.blob_radius, reach = p.r_max + a + ext + 0.1;
+    const double ext = 0.5 * (E - 1) * std::sqrt(3.0);
+    const double a = p.blob_radius;
     struct Est { int tile; double cost; };
     std::vector<Est> tiles;
     double total = 0.0;
+    const double R = p.r_max + a + 1e-3;   // no voxel at |v| >= R receives anything
     for (int tz = 0; tz < TZ; ++tz)
         for (int ty = 0; ty < TY; ++ty)
             for (int tx = 0; tx < TX; ++tx) {
-                const double cx = E * tx + half, cy = E * ty + half - h, cz = E * tz + half - h;
+                // voxel box of the tile clipped to the half box
+                const double x0 = E * tx, x1 = std::min(x0 + E - 1, static_cast<double>(h));
+                const double y0 = E * ty - h, y1 = std::min(y0 + E - 1, static_cast<double>(h));
+                const double z0 = E * tz - h, z1 = std::min(z0 + E - 1, static_cast<double>(h));
+                auto closest = [](double lo, double hi) { return lo > 0 ? lo : (hi < 0 ? hi : 0.0); };
+                const double qx = closest(x0, x1), qy = closest(y0, y1), qz = closest(z0, z1);
+                if (qx * qx + qy * qy + qz * qz >= R * R) continue;
+                const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1), cz = 0.5 * (z0 + z1);
                 const double r = std::sqrt(cx * cx + cy * cy + cz * cz);
-                if (r > reach) continue;
+                const double vol = (x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) / (E * E * E);
                 const double frac = std::min(1.0, (a + ext) / std::max(r, 1e-9));
-                const double cost = frac * p.max_batch;
+                const double cost = frac * p.max_batch * (E == 8 ? std::max(vol, 0.25) : 1.0);
                 tiles.push_back({tx + TX * (ty + TY * tz), cost});
                 total += cost;
             }
@@ -197,10 +206,38 @@ recon_config default_config()
     c.group = 1;
     c.inner_chunk = 32;
     c.split = 32;
+    c.slab_flags = 4 | 2;
     return c;
 }
 
 int default_waves(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 16; }
+
+// State of a dynamic-tuning search (random search over the tuning space).
+struct TuneState {
+    bool active = false;
+    std::vector<recon_config> space;
+    std::vector<int> order;       // random permutation of space indices
+    size_t next = 0;              // next position in order
+    int max_steps = 0;
+    double target = 0.0;
+    int steps_done = 0;
+    int pending = -1;             // space index of the step in flight
+    int pending_count = 0;        // slices of that step
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<double> ns;       // ns per slice per space index (< 0: not measured)
+    int best = -1;
+    double best_ns = std::numeric_limits<double>::infinity();
+    double sum_ns = 0.0;
+};
+
+// splitmix64: the random search's generator (seeded, reproducible)
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
 
 }  // namespace
 
@@ -221,7 +258,12 @@ struct recon_ctx {
     int max_threads;
     hipEvent_t ev_start;  // optional timing events around the insertion kernel
     hipEvent_t ev_stop;
+    TuneState tune;
 };
+
+static recon_status tune_collect(recon_ctx *c);
+static recon_status tune_finish(recon_ctx *c);
+static recon_status apply_config(recon_ctx *c, const recon_config &n);
 
 extern "C" {
 
@@ -313,6 +355,8 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->g.tscale = static_cast<float>((p->table_size - 1) /
                                      (static_cast<double>(p->blob_radius) * p->blob_radius));
     c->g.r2max = p->r_max * p->r_max;
+    c->g.dtype = p->slice_dtype;
+    c->g.scales = nullptr;
     if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
         // blob table too large for the slab kernel's LDS budget
         c->cfg.variant = static_cast<size_t>(p->table_size) * sizeof(float2) <= c->max_lds ? RECON_VARIANT_BINNED
@@ -369,21 +413,49 @@ recon_status recon_reset(recon_ctx *c)
 recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float *d_scales, const float *d_quats,
                                 int32_t count)
 {
-    (void)d_scales;
     if (!c) return fail(RECON_EINVAL, "ctx is NULL");
     if (count < 0 || count > c->p.max_batch)
         return fail(RECON_EINVAL, "count must be in [0, max_batch=%d] (got %d)", c->p.max_batch, count);
     if (count == 0) return RECON_OK;
     if (!d_slices || !d_quats) return fail(RECON_EINVAL, "slices and quaternions must be non-NULL");
+    if (c->p.slice_dtype == RECON_SLICE_F16 && !d_scales)
+        return fail(RECON_EINVAL, "half-precision slices need per-slice scales");
+    c->g.scales = c->p.slice_dtype == RECON_SLICE_F16 ? d_scales : nullptr;
+    // dynamic tuning: measure the previous step, then pick this step's configuration
+    bool tuning_step = false;
+    if (c->tune.active || c->tune.pending >= 0) {
+        recon_status st = tune_collect(c);
+        if (st != RECON_OK) return st;
+        TuneState &t = c->tune;
+        if (t.active) {
+            const bool done = t.steps_done >= t.max_steps || t.next >= t.order.size() ||
+                              (t.target > 0.0 && t.best >= 0 && t.best_ns <= t.target);
+            if (done) {
+                st = tune_finish(c);
+                if (st != RECON_OK) return st;
+            } else {
+                const int idx = t.order[t.next++];
+                st = apply_config(c, t.space[idx]);
+                if (st != RECON_OK) return st;
+                t.pending = idx;
+                t.pending_count = count;
+                tuning_step = true;
+            }
+        }
+    }
     Counters *ctr = reinterpret_cast<Counters *>(c->ws + c->L.ctr);
     Orient *orient = reinterpret_cast<Orient *>(c->ws + c->L.orient);
     const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
-    const float2 *slices = static_cast<const float2 *>(d_slices);
+    const void *slices = d_slices;
     hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
     if (c->ev_start) {
         e = hipEventRecord(c->ev_start, c->stream);
         if (e != hipSuccess) return hip_fail(e, "record start event");
+    }
+    if (tuning_step) {
+        e = hipEventRecord(c->tune.ev0, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "record tuning start event");
     }
     if (c->cfg.variant == RECON_VARIANT_NAIVE) {
         e = recon::launch_insert_naive(c->g, c->p.table_lerp != 0, slices, orient, count, table,
@@ -393,6 +465,10 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
             e = hipEventRecord(c->ev_stop, c->stream);
             if (e != hipSuccess) return hip_fail(e, "record stop event");
         }
+        if (tuning_step) {
+            e = hipEventRecord(c->tune.ev1, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
+        }
         return RECON_OK;
     }
     const Item *items = reinterpret_cast<const Item *>(c->ws + c->L.items);
@@ -401,7 +477,8 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     const int blocks = c->num_cu;
     const bool slab = c->cfg.variant == RECON_VARIANT_SLAB;
     if (slab)
-        e = recon::launch_insert_slab(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
+        e = recon::launch_insert_slab(c->g, c->p.table_lerp != 0, c->cfg.slab_flags & 3, slices, orient, count, table,
+                                      items, nitems,
                                       partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G, c->W,
                                       c->stream);
     else
@@ -412,6 +489,10 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     if (c->ev_stop) {
         e = hipEventRecord(c->ev_stop, c->stream);
         if (e != hipSuccess) return hip_fail(e, "record stop event");
+    }
+    if (tuning_step) {
+        e = hipEventRecord(c->tune.ev1, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
     }
     if (c->plan.nslots > 0) {
         e = slab ? recon::launch_reduce_partials8(c->g, items, nitems, partials, c->G, c->W, c->stream)
@@ -432,9 +513,12 @@ recon_status recon_finalize(recon_ctx *c, void *d_V, float w_threshold)
     return RECON_OK;
 }
 
-recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
+}  // extern "C"
+
+// Fills library defaults into a configuration and checks it against the
+// device's limits; no side effects.
+static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, recon_config *out)
 {
-    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
     recon_config d = default_config();
     recon_config n = cfg ? *cfg : d;
     if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
@@ -442,6 +526,8 @@ recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
     if (n.group == 0) n.group = d.group;
     if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
     if (n.split == 0) n.split = d.split;
+    if (n.slab_flags == 0) n.slab_flags = d.slab_flags;
+    if (n.slab_flags < 4 || n.slab_flags > 7) return fail(RECON_ECONFIG, "slab_flags must be 4 | bits, bits in [0, 3]");
     if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED && n.variant != RECON_VARIANT_SLAB)
         return fail(RECON_ECONFIG, "unknown variant %d", n.variant);
     const int wpb = n.waves_per_block;
@@ -454,15 +540,198 @@ recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
     if (n.variant == RECON_VARIANT_BINNED &&
         static_cast<size_t>(c->p.table_size) * sizeof(float2) > c->max_lds)
         return fail(RECON_ECONFIG, "blob table of %d entries does not fit in LDS", c->p.table_size);
+    if (n.variant == RECON_VARIANT_SLAB && wpb > 8)
+        return fail(RECON_ECONFIG, "slab kernel runs at most 8 waves per work-group");
     if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, wpb) > c->max_lds)
         return fail(RECON_ECONFIG, "slab kernel needs %zu bytes of LDS with %d waves (device: %zu)",
                     recon::slab_lds_bytes(c->g, wpb), wpb, c->max_lds);
+    *out = n;
+    return RECON_OK;
+}
+
+// Makes a resolved configuration current (re-plans and uploads the work
+// plan when the tiling or the split changes; that upload synchronises).
+static recon_status apply_config(recon_ctx *c, const recon_config &n)
+{
     const bool replan = n.split != c->cfg.split || tile_edge(n.variant) != tile_edge(c->cfg.variant);
     c->cfg = n;
     if (replan) {
         c->plan = make_plan(c->p, n.split, tile_edge(n.variant));
         return upload_plan(c);
     }
+    return RECON_OK;
+}
+
+// The tuning space: every runnable combination of the kernel knobs.
+static std::vector<recon_config> tuning_space(const recon_ctx *c)
+{
+    std::vector<recon_config> out;
+    const int variants[3] = {RECON_VARIANT_SLAB, RECON_VARIANT_BINNED, RECON_VARIANT_NAIVE};
+    for (int v : variants) {
+        std::vector<int> waves = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 8}
+                                 : v == RECON_VARIANT_BINNED ? std::vector<int>{8, 16}
+                                                             : std::vector<int>{4, 8, 16};
+        std::vector<int> splits = v == RECON_VARIANT_NAIVE ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
+        std::vector<int> flags = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{6};
+        for (int wpb : waves)
+            for (int inner : {16, 32, 64})
+                for (int sp : splits)
+                    for (int fl : flags) {
+                        recon_config in;
+                        std::memset(&in, 0, sizeof(in));
+                        in.variant = v;
+                        in.waves_per_block = wpb;
+                        in.group = 1;
+                        in.inner_chunk = inner;
+                        in.split = sp;
+                        in.slab_flags = fl;
+                        recon_config r;
+                        const std::string keep = g_err;
+                        if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
+                        g_err = keep;
+                    }
+    }
+    return out;
+}
+
+static recon_status tune_collect(recon_ctx *c)
+{
+    TuneState &t = c->tune;
+    if (t.pending < 0) return RECON_OK;
+    hipError_t e = hipEventSynchronize(t.ev1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.ev0, t.ev1);
+    if (e != hipSuccess) return hip_fail(e, "tuning step timing");
+    const double ns = 1e6 * static_cast<double>(ms) / std::max(1, t.pending_count);
+    t.ns[t.pending] = ns;
+    t.sum_ns += ns;
+    ++t.steps_done;
+    if (ns < t.best_ns) {
+        t.best_ns = ns;
+        t.best = t.pending;
+    }
+    t.pending = -1;
+    return RECON_OK;
+}
+
+static recon_status tune_finish(recon_ctx *c)
+{
+    TuneState &t = c->tune;
+    recon_status st = tune_collect(c);
+    if (st != RECON_OK) return st;
+    t.active = false;
+    if (t.best >= 0) return apply_config(c, t.space[t.best]);
+    return RECON_OK;
+}
+
+static void tune_release(recon_ctx *c)
+{
+    if (c->tune.ev0) (void)hipEventDestroy(c->tune.ev0);
+    if (c->tune.ev1) (void)hipEventDestroy(c->tune.ev1);
+    c->tune.ev0 = c->tune.ev1 = nullptr;
+}
+
+extern "C" {
+
+recon_status recon_set_config(recon_ctx *c, const recon_config *cfg)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    recon_config n;
+    recon_status st = resolve_config(c, cfg, &n);
+    if (st != RECON_OK) return st;
+    return apply_config(c, n);
+}
+
+recon_status recon_tune_space_size(const recon_ctx *c, int32_t *size)
+{
+    if (!c || !size) return fail(RECON_EINVAL, "NULL argument");
+    *size = static_cast<int32_t>(tuning_space(c).size());
+    return RECON_OK;
+}
+
+recon_status recon_tune_space_config(const recon_ctx *c, int32_t index, recon_config *out)
+{
+    if (!c || !out) return fail(RECON_EINVAL, "NULL argument");
+    const std::vector<recon_config> sp = tuning_space(c);
+    if (index < 0 || index >= static_cast<int32_t>(sp.size()))
+        return fail(RECON_EINVAL, "index %d outside the tuning space (size %zu)", index, sp.size());
+    *out = sp[index];
+    return RECON_OK;
+}
+
+recon_status recon_tune_begin(recon_ctx *c, const recon_tune_opts *opts)
+{
+    if (!c || !opts) return fail(RECON_EINVAL, "NULL argument");
+    if (opts->max_steps < 0) return fail(RECON_EINVAL, "max_steps must be >= 0");
+    if (!(opts->target_ns_per_slice >= 0.0)) return fail(RECON_EINVAL, "target must be >= 0");
+    recon_status st = tune_collect(c);
+    if (st != RECON_OK) return st;
+    TuneState &t = c->tune;
+    if (!t.ev0) {
+        hipError_t e = hipEventCreate(&t.ev0);
+        if (e == hipSuccess) e = hipEventCreate(&t.ev1);
+        if (e != hipSuccess) return hip_fail(e, "create tuning events");
+    }
+    t.space = tuning_space(c);
+    if (t.space.empty()) return fail(RECON_ECONFIG, "empty tuning space on this device");
+    const int n = static_cast<int>(t.space.size());
+    t.order.resize(n);
+    for (int i = 0; i < n; ++i) t.order[i] = i;
+    uint64_t x = opts->seed;
+    for (int i = n - 1; i > 0; --i) {
+        const int j = static_cast<int>(splitmix64(x) % static_cast<uint64_t>(i + 1));
+        std::swap(t.order[i], t.order[j]);
+    }
+    t.next = 0;
+    t.max_steps = opts->max_steps == 0 ? n : std::min(opts->max_steps, n);
+    t.target = opts->target_ns_per_slice;
+    t.steps_done = 0;
+    t.pending = -1;
+    t.ns.assign(n, -1.0);
+    t.best = -1;
+    t.best_ns = std::numeric_limits<double>::infinity();
+    t.sum_ns = 0.0;
+    t.active = true;
+    return RECON_OK;
+}
+
+recon_status recon_tune_get_info(recon_ctx *c, recon_tune_info *info)
+{
+    if (!c || !info) return fail(RECON_EINVAL, "NULL argument");
+    recon_status st = tune_collect(c);
+    if (st != RECON_OK) return st;
+    const TuneState &t = c->tune;
+    std::memset(info, 0, sizeof(*info));
+    info->active = t.active ? 1 : 0;
+    info->steps_done = t.steps_done;
+    info->space_size = static_cast<int32_t>(t.space.empty() ? tuning_space(c).size() : t.space.size());
+    info->best_index = t.best;
+    info->best_ns_per_slice = t.best >= 0 ? t.best_ns : 0.0;
+    info->mean_ns_per_slice = t.steps_done > 0 ? t.sum_ns / t.steps_done : 0.0;
+    if (t.best >= 0) info->best = t.space[t.best];
+    return RECON_OK;
+}
+
+recon_status recon_tune_end(recon_ctx *c)
+{
+    if (!c) return fail(RECON_EINVAL, "ctx is NULL");
+    return tune_finish(c);
+}
+
+recon_status recon_tune_invocations(double rp, double s, double t_avg, double t_well, double *n)
+{
+    if (!n) return fail(RECON_EINVAL, "NULL argument");
+    if (!(rp > 0.0 && rp < 1.0) || !(s >= 0.0) || !(t_well > 0.0) || !(t_avg >= 0.0))
+        return fail(RECON_EINVAL, "need 0 < rp < 1, s >= 0, t_avg >= 0, t_well > 0");
+    *n = rp * s * (t_avg / t_well - 1.0) / (1.0 - rp);
+    return RECON_OK;
+}
+
+recon_status recon_tune_steps(double r, double p, double *s)
+{
+    if (!s) return fail(RECON_EINVAL, "NULL argument");
+    if (!(r > 0.0 && r < 1.0) || !(p >= 0.0 && p < 1.0)) return fail(RECON_EINVAL, "need 0 < r < 1 and 0 <= p < 1");
+    *s = std::log1p(-p) / std::log1p(-r);
     return RECON_OK;
 }
 
@@ -501,6 +770,11 @@ recon_status recon_stats(recon_ctx *c, uint64_t *inserted, uint64_t *rejected)
     return RECON_OK;
 }
 
-void recon_destroy(recon_ctx *c) { delete c; }
+void recon_destroy(recon_ctx *c)
+{
+    if (!c) return;
+    tune_release(c);
+    delete c;
+}
 
 }  // extern "C"

@@ -36,12 +36,21 @@ constexpr int LIST_WORDS = TV / 2;     // 512 uint16 voxel ids
 
 template <int WIN>
 struct SlabShape {
-    static constexpr int RECT = WIN + 16;   // >= 2 * 3.5 * sqrt(3) + WIN + 3
+    // The rectangle must hold every window of the tile: its width is at most
+    // 2 * ext + 2a + 4 with ext <= 3.5 * sqrt(3) (half the tile diagonal
+    // projected on a slice axis) and WIN = floor(2a) + 1, so WIN + 17 cells
+    // always suffice.
+    static constexpr int RECT = WIN + 17;
     static constexpr int RECT2 = RECT * RECT;
     static constexpr int WAVE_WORDS = ACC_WORDS + 2 * RECT2 + LIST_WORDS;
 };
 
-__host__ __device__ inline int table_words(int N) { return (N + 1 + 3) & ~3; }
+// Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^20 T[N-1].
+// With i = min(floor(t), N) and w = max(T[i] + frac(t) (T[i+1] - T[i]), 0),
+// t = N-1 gives exactly T[N-1], and any representable t > N-1 gives 0 (the
+// sentinel slope exceeds T[N-1] by 2^20 while frac(t) >= 2^-10 there), so the
+// blob's inclusive cut-off at d^2 = a^2 costs no compare.
+__host__ __device__ inline int table_words(int N) { return (N + 2 + 3) & ~3; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -59,69 +68,107 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
     return i == 0 ? x : (i == 1 ? y : z);
 }
 
-// Window of one (voxel, slice) hit from the LDS rectangle whose cell (0, 0)
-// is sample (kx_lo, ky_lo).  RIM: the rectangle reaches the disk edge, so
-// each candidate's |k| < r_max membership is checked for the weight sum.
-template <int WIN, bool RIM, bool LERP>
+// Window of one (voxel, slice) hit from the LDS rectangle (row stride RECT)
+// whose cell (0, 0) is sample (kx_lo, ky_lo).  All LDS reads of the window
+// are issued before any is consumed.  RIM: the rectangle reaches the disk
+// edge, so each candidate's |k| < r_max membership gates its weight.
+template <int WIN, bool RIM, bool LERP, bool PRELOAD>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
-                                           const Geom &g, float tmax, float ux, float uy, float uz,
-                                           int kx_lo, int ky_lo, float &pr, float &pi, float &pw)
+                                           const Geom &g, float ux, float uy, float uz, float kx_lo,
+                                           float ky_lo, float &pr, float &pi, float &pw)
 {
     constexpr int RECT = SlabShape<WIN>::RECT;
-    const int kx0 = static_cast<int>(ceilf(ux - g.a));
-    const int ky0 = static_cast<int>(ceilf(uy - g.a));
-    const int ox = min(max(kx0 - kx_lo, 0), RECT - WIN);
-    const int oy = min(max(ky0 - ky_lo, 0), RECT - WIN);
+    const float span = static_cast<float>(RECT - WIN);
+    // first window column / row as floats, kept inside the staged rectangle
+    const float fx0 = fminf(fmaxf(ceilf(ux - g.a), kx_lo), kx_lo + span);
+    const float fy0 = fminf(fmaxf(ceilf(uy - g.a), ky_lo), ky_lo + span);
+    const int ox = static_cast<int>(fx0 - kx_lo);
+    const int oy = static_cast<int>(fy0 - ky_lo);
     const float2 *base = rect + oy * RECT + ox;
+    const float ts = g.tscale;
     float dxs[WIN], dys[WIN];
-    int kx2[WIN], ky2[WIN];
     const float uzs = uz * uz;
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {
-        const int kx = kx_lo + ox + i;
-        const float dx = ux - static_cast<float>(kx);
-        dxs[i] = dx * dx * g.tscale;
-        const int ky = ky_lo + oy + i;
-        const float dy = uy - static_cast<float>(ky);
-        dys[i] = fmaf(dy, dy, uzs) * g.tscale;
-        if (RIM) {
-            kx2[i] = kx * kx;
-            ky2[i] = ky * ky;
-        }
+        const float dx = ux - (fx0 + static_cast<float>(i));
+        dxs[i] = dx * dx * ts;
+        const float dy = uy - (fy0 + static_cast<float>(i));
+        dys[i] = fmaf(dy, dy, uzs) * ts;
     }
     float sr = 0.f, si = 0.f, sw = 0.f;
-#pragma unroll
-    for (int j = 0; j < WIN; ++j) {
-#pragma unroll
-        for (int i = 0; i < WIN; ++i) {
-            const float t = dxs[i] + dys[j];
-            const float tc = fminf(t, tmax);
-            const int it = static_cast<int>(tc);
-            float w;
-            if (LERP) {
-                const float f = tc - static_cast<float>(it);
-                const float t0 = tab[it], t1 = tab[it + 1];
-                w = fmaf(f, t1 - t0, t0);
-            } else {
-                w = tab[it];
-            }
-            bool ok = t <= tmax;
-            if (RIM) ok = ok && static_cast<float>(kx2[i] + ky2[j]) < g.r2max;
-            w = ok ? w : 0.f;
-            const float2 f2 = base[j * RECT + i];
-            sr = fmaf(w, f2.x, sr);
-            si = fmaf(w, f2.y, si);
-            sw += w;
+    auto weight = [&](float tk, float t0k, float t1k, int i, int j) {
+        float w;
+        if (LERP) {
+            const float f = __builtin_amdgcn_fractf(tk);
+            w = fmaxf(fmaf(f, t1k - t0k, t0k), 0.f);
+        } else {
+            w = tk <= static_cast<float>(g.N - 1) ? t0k : 0.f;
         }
+        if (RIM) {
+            const float kx = fx0 + static_cast<float>(i), ky = fy0 + static_cast<float>(j);
+            w = fmaf(kx, kx, ky * ky) < g.r2max ? w : 0.f;
+        }
+        return w;
+    };
+    if (PRELOAD) {
+        // every LDS read of the window is issued before any is consumed
+        float t[WIN * WIN];
+        unsigned idx[WIN * WIN];
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) {
+                t[j * WIN + i] = dxs[i] + dys[j];
+                idx[j * WIN + i] = min(static_cast<unsigned>(t[j * WIN + i]), static_cast<unsigned>(g.N));
+            }
+        float t0[WIN * WIN], t1[WIN * WIN];
+        float2 fv[WIN * WIN];
+#pragma unroll
+        for (int k = 0; k < WIN * WIN; ++k) {
+            t0[k] = tab[idx[k]];
+            t1[k] = LERP ? tab[idx[k] + 1] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) fv[j * WIN + i] = base[j * RECT + i];
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) {
+                const int k = j * WIN + i;
+                const float w = weight(t[k], t0[k], t1[k], i, j);
+                sr = fmaf(w, fv[k].x, sr);
+                si = fmaf(w, fv[k].y, si);
+                sw += w;
+            }
+    } else {
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) {
+                const float tk = dxs[i] + dys[j];
+                const unsigned ik = min(static_cast<unsigned>(tk), static_cast<unsigned>(g.N));
+                const float w = weight(tk, tab[ik], LERP ? tab[ik + 1] : 0.f, i, j);
+                const float2 f2 = base[j * RECT + i];
+                sr = fmaf(w, f2.x, sr);
+                si = fmaf(w, f2.y, si);
+                sw += w;
+            }
     }
     pr = sr;
     pi = si;
     pw = sw;
 }
 
-template <int WIN, bool LERP>
-__global__ __launch_bounds__(1024) void k_insert_slab(
-    Geom g, const float2 *__restrict__ slices, const Orient *__restrict__ orient, int count,
+// Variant flags of the slab kernel (tuning knobs).
+constexpr int SLAB_ATOMIC = 1;    // LDS float atomics for the accumulators (else read-add-write)
+constexpr int SLAB_PRELOAD = 2;   // issue all window reads before use
+constexpr int SLAB_DEFAULT = SLAB_PRELOAD;
+
+template <int WIN, bool LERP, int FLAGS>
+__global__ __launch_bounds__(512) void k_insert_slab(
+    Geom g, const void *__restrict__ slices, const Orient *__restrict__ orient, int count,
     const float2 *__restrict__ table_g, const Item *__restrict__ items, int nitems,
     float4 *__restrict__ partials, int inner_chunk, Counters *__restrict__ ctr,
     float2 *__restrict__ G, float *__restrict__ W)
@@ -129,10 +176,15 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
     using SS = SlabShape<WIN>;
     constexpr int RECT = SS::RECT;
     constexpr int RECT2 = SS::RECT2;
+    constexpr int NC = (RECT2 + 63) / 64;
     extern __shared__ float smem[];
     float *tab = smem;
     for (int i = threadIdx.x; i < g.N; i += blockDim.x) tab[i] = table_g[i].x;
-    if (threadIdx.x == 0) tab[g.N] = table_g[g.N - 1].x;
+    if (threadIdx.x == 0) {
+        const float sentinel = -1048576.0f * table_g[g.N - 1].x;
+        tab[g.N] = sentinel;
+        tab[g.N + 1] = sentinel;
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -147,9 +199,9 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
     const int TX = (g.h + 1 + TE - 1) / TE;
     const int TY = (g.dim + TE - 1) / TE;
     const size_t slen = static_cast<size_t>(g.n) * g.sw;
-    const float reach = sqrtf(g.r2max) + g.a + 3.5f * 1.7320508f + 0.01f;
-    const float reach2 = reach * reach;
-    const float tmax = static_cast<float>(g.N - 1);
+    const float rmax = sqrtf(g.r2max);
+    // voxels with |v| >= r_max + a receive nothing (every sample has |p| < r_max)
+    const float R2 = (rmax + g.a + 1e-3f) * (rmax + g.a + 1e-3f);
     const float a_run = g.a * (1.0f + 1e-5f) + 1e-5f;
 
     for (;;) {
@@ -161,8 +213,13 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
         const int tx = item.tile % TX;
         const int ty = (item.tile / TX) % TY;
         const int tz = item.tile / (TX * TY);
+        // voxel box of the tile, clipped to the half box
         const int X0 = TE * tx, Y0 = TE * ty - g.h, Z0 = TE * tz - g.h;
-        const float cx = X0 + 3.5f, cy = Y0 + 3.5f, cz = Z0 + 3.5f;
+        const int X1 = min(X0 + TE - 1, g.h), Y1 = min(Y0 + TE - 1, g.h), Z1 = min(Z0 + TE - 1, g.h);
+        const float cx = 0.5f * (X0 + X1), cy = 0.5f * (Y0 + Y1), cz = 0.5f * (Z0 + Z1);
+        const float hx = 0.5f * (X1 - X0), hy = 0.5f * (Y1 - Y0), hz = 0.5f * (Z1 - Z0);
+        const float reach = rmax + g.a + sqrtf(hx * hx + hy * hy + hz * hz) + 0.01f;
+        const float reach2 = reach * reach;
         const int s0 = static_cast<int>(static_cast<long>(count) * item.part / item.nparts);
         const int s1 = static_cast<int>(static_cast<long>(count) * (item.part + 1) / item.nparts);
 
@@ -173,98 +230,167 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
         int inner = 0;
         wave_sync();
 
-        for (int base0 = s0; base0 < s1; base0 += 64) {
-            const int sl = base0 + lane;
-            bool pass = false;
-            if (sl < s1) {
-                const Orient o = orient[sl];
-                if (o.e1.w != 0.f) {
-                    const float dz = fmaf(o.e3.x, cx, fmaf(o.e3.y, cy, o.e3.z * cz));
-                    const float ext = 3.5f * (fabsf(o.e3.x) + fabsf(o.e3.y) + fabsf(o.e3.z));
-                    const float px = fmaf(o.e1.x, cx, fmaf(o.e1.y, cy, o.e1.z * cz));
-                    const float py = fmaf(o.e2.x, cx, fmaf(o.e2.y, cy, o.e2.z * cz));
-                    pass = fabsf(dz) <= g.a + ext + 1e-3f && fmaf(px, px, py * py) <= reach2;
+        // Iterator over the item's slices that pass the tile's bin test: a
+        // ballot over 64 slices at a time (wave-uniform state).
+        int it_base = s0 - 64;
+        unsigned long long it_mask = 0ull;
+        auto next_slice = [&]() -> int {
+            while (it_mask == 0ull) {
+                it_base += 64;
+                if (it_base >= s1) return -1;
+                const int sl = it_base + lane;
+                bool pass = false;
+                if (sl < s1) {
+                    const Orient o = orient[sl];
+                    if (o.e1.w != 0.f) {
+                        const float dz = fmaf(o.e3.x, cx, fmaf(o.e3.y, cy, o.e3.z * cz));
+                        const float ext = fmaf(hx, fabsf(o.e3.x), fmaf(hy, fabsf(o.e3.y), hz * fabsf(o.e3.z)));
+                        const float px = fmaf(o.e1.x, cx, fmaf(o.e1.y, cy, o.e1.z * cz));
+                        const float py = fmaf(o.e2.x, cx, fmaf(o.e2.y, cy, o.e2.z * cz));
+                        pass = fabsf(dz) <= g.a + ext + 1e-3f && fmaf(px, px, py * py) <= reach2;
+                    }
+                }
+                it_mask = __ballot(pass);
+            }
+            const int b = __builtin_ctzll(it_mask);
+            it_mask &= it_mask - 1ull;
+            return __builtin_amdgcn_readfirstlane(it_base + b);
+        };
+
+        // Staging of one slice, split into issue (global loads into registers)
+        // and commit (LDS writes) so that the next slice's loads are in flight
+        // while the current slice's windows are evaluated.
+        struct Stage {
+            float4 e1, e2, e3;
+            int kx_lo, ky_lo;
+            bool rim;
+        };
+        float2 cell[NC];
+        bool keep[NC];
+        int dst[NC];
+        auto issue = [&](int s, Stage &st) {
+            const Orient o = orient[s];
+            st.e1 = o.e1;
+            st.e2 = o.e2;
+            st.e3 = o.e3;
+            const float ucx = fmaf(o.e1.x, cx, fmaf(o.e1.y, cy, o.e1.z * cz));
+            const float ucy = fmaf(o.e2.x, cx, fmaf(o.e2.y, cy, o.e2.z * cz));
+            const float extx = fmaf(hx, fabsf(o.e1.x), fmaf(hy, fabsf(o.e1.y), hz * fabsf(o.e1.z)));
+            const float exty = fmaf(hx, fabsf(o.e2.x), fmaf(hy, fabsf(o.e2.y), hz * fabsf(o.e2.z)));
+            const int kx_lo = static_cast<int>(floorf(ucx - extx - g.a)) - 1;
+            const int ky_lo = static_cast<int>(floorf(ucy - exty - g.a)) - 1;
+            const int wx = min(static_cast<int>(floorf(ucx + extx + g.a)) + 2 - kx_lo, RECT);
+            const int wy = min(static_cast<int>(floorf(ucy + exty + g.a)) + 2 - ky_lo, RECT);
+            const int fxm = max(abs(kx_lo), abs(kx_lo + wx - 1));
+            const int fym = max(abs(ky_lo), abs(ky_lo + wy - 1));
+            st.kx_lo = kx_lo;
+            st.ky_lo = ky_lo;
+            st.rim = !(static_cast<float>(fxm * fxm + fym * fym) < g.r2max);
+            const int ncell = wx * wy;
+            const float inv_wx = 1.0f / static_cast<float>(wx);
+            // buffer resource over this slice: 32-bit offsets, hardware bounds check
+            const int eb = sample_bytes(g.dtype);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<unsigned char *>(static_cast<const unsigned char *>(slices) +
+                                            static_cast<size_t>(s) * slen * eb),
+                static_cast<short>(0), static_cast<int>(slen * eb), 0x00020000);
+            const float sscale = g.scales ? g.scales[s] : 1.0f;
+#pragma unroll
+            for (int qq = 0; qq < NC; ++qq) {
+                const int c = qq * 64 + lane;
+                const int cy_ = static_cast<int>((static_cast<float>(c) + 0.5f) * inv_wx);
+                const int cx_ = c - cy_ * wx;
+                const int kx = kx_lo + cx_, ky = ky_lo + cy_;
+                const bool valid = c < ncell && static_cast<float>(kx * kx + ky * ky) < g.r2max;
+                const bool direct = kx > 0 || (kx == 0 && ky >= 0);
+                int row = direct ? ky + g.h : g.h - ky;
+                int col = direct ? kx : -kx;
+                row = valid ? row : g.h;
+                col = valid ? col : 0;
+                const int e = row * g.sw + col;
+                if (g.dtype == 0) {
+                    cell[qq] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, e * 8, 0, 0));
+                } else {
+                    const unsigned raw = __builtin_amdgcn_raw_buffer_load_b32(rs, e * 4, 0, 0);
+                    if (g.dtype == 1) {
+                        const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
+                        const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
+                        cell[qq] = make_float2(static_cast<float>(lo) * sscale, static_cast<float>(hi) * sscale);
+                    } else {
+                        cell[qq] = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
+                    }
+                }
+                // the sign flip of mirrored samples is applied at commit
+                keep[qq] = valid;
+                dst[qq] = c < ncell ? (direct ? 1 : -1) * (cy_ * RECT + cx_ + 1) : 0;
+            }
+        };
+        auto commit = [&]() {
+#pragma unroll
+            for (int qq = 0; qq < NC; ++qq) {
+                if (dst[qq] != 0) {
+                    float2 v = keep[qq] ? cell[qq] : make_float2(0.f, 0.f);
+                    if (dst[qq] < 0) v.y = -v.y;
+                    rect[abs(dst[qq]) - 1] = v;
                 }
             }
-            unsigned long long mask = __ballot(pass);
-            while (mask) {
-                const int b = __builtin_ctzll(mask);
-                mask &= mask - 1ull;
-                const int s = base0 + b;
-                const Orient o = orient[s];
-                const float2 *Fs = slices + s * slen;
+        };
 
-                // 1. stage the rectangle of samples the tile's windows can touch
-                const float ucx = fmaf(o.e1.x, cx, fmaf(o.e1.y, cy, o.e1.z * cz));
-                const float ucy = fmaf(o.e2.x, cx, fmaf(o.e2.y, cy, o.e2.z * cz));
-                const float extx = 3.5f * (fabsf(o.e1.x) + fabsf(o.e1.y) + fabsf(o.e1.z));
-                const float exty = 3.5f * (fabsf(o.e2.x) + fabsf(o.e2.y) + fabsf(o.e2.z));
-                const int kx_lo = static_cast<int>(floorf(ucx - extx - g.a)) - 1;
-                const int ky_lo = static_cast<int>(floorf(ucy - exty - g.a)) - 1;
-                const int fx = max(abs(kx_lo), abs(kx_lo + RECT - 1));
-                const int fy = max(abs(ky_lo), abs(ky_lo + RECT - 1));
-                const bool rim = !(static_cast<float>(fx * fx + fy * fy) < g.r2max);
-                constexpr int NC = (RECT2 + 63) / 64;
-                float2 cell[NC];
-                bool keep[NC];
+        Stage cur;
+        int s = next_slice();
+        if (s >= 0) issue(s, cur);
+        while (s >= 0) {
+            // 1. enumerate the tile's voxels inside the slab |e3.v| <= a
+            //    (and inside the reach sphere |v| < r_max + a)
+            const float4 e3 = cur.e3;
+            const float n0 = fabsf(e3.x), n1 = fabsf(e3.y), n2 = fabsf(e3.z);
+            const int d = (n0 >= n1 && n0 >= n2) ? 0 : (n1 >= n2 ? 1 : 2);
+            const int ia = d == 0 ? 1 : 0;
+            const int ib = d == 2 ? 1 : 2;
+            const float nd = sel3(d, e3.x, e3.y, e3.z);
+            const float na = sel3(ia, e3.x, e3.y, e3.z);
+            const float nb = sel3(ib, e3.x, e3.y, e3.z);
+            const int D0 = sel3i(d, X0, Y0, Z0), D1 = sel3i(d, X1, Y1, Z1);
+            const int A0 = sel3i(ia, X0, Y0, Z0), A1 = sel3i(ia, X1, Y1, Z1);
+            const int B0 = sel3i(ib, X0, Y0, Z0), B1 = sel3i(ib, X1, Y1, Z1);
+            const int sd = sel3i(d, 1, TE, TE * TE);
+            const int sa = sel3i(ia, 1, TE, TE * TE);
+            const int sb = sel3i(ib, 1, TE, TE * TE);
+            const int ca = lane & (TE - 1), cb = lane >> 3;
+            const int va = A0 + ca, vb = B0 + cb;
+            const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
+            const float rem = R2 - fmaf(fva, fva, fvb * fvb);
+            const bool col_in = va <= A1 && vb <= B1 && rem >= 0.f;
+            const float lim = sqrtf(fmaxf(rem, 0.f));
+            const float q = fmaf(na, fva, nb * fvb);
+            const float inv = 1.0f / nd;
+            const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
+            const int lo = max(static_cast<int>(ceilf(fmaxf(fminf(t1, t2), -lim))), D0);
+            const int hi = min(static_cast<int>(floorf(fminf(fmaxf(t1, t2), lim))), D1);
+            const int cnt = col_in ? max(hi - lo + 1, 0) : 0;
+            int incl = cnt;
 #pragma unroll
-                for (int q = 0; q < NC; ++q) {
-                    const int c = q * 64 + lane;
-                    const int cy_ = c / RECT, cx_ = c - cy_ * RECT;
-                    const int kx = kx_lo + cx_, ky = ky_lo + cy_;
-                    const bool valid = c < RECT2 && static_cast<float>(kx * kx + ky * ky) < g.r2max;
-                    const bool direct = kx > 0 || (kx == 0 && ky >= 0);
-                    int row = direct ? ky + g.h : g.h - ky;
-                    int col = direct ? kx : -kx;
-                    row = valid ? row : g.h;
-                    col = valid ? col : 0;
-                    cell[q] = Fs[row * g.sw + col];
-                    cell[q].y = direct ? cell[q].y : -cell[q].y;
-                    keep[q] = valid;
-                }
-#pragma unroll
-                for (int q = 0; q < NC; ++q) {
-                    const int c = q * 64 + lane;
-                    if (q < NC - 1 || c < RECT2) rect[c] = keep[q] ? cell[q] : make_float2(0.f, 0.f);
-                }
-
-                // 2. enumerate the tile's voxels inside the slab |e3.v| <= a
-                const float n0 = fabsf(o.e3.x), n1 = fabsf(o.e3.y), n2 = fabsf(o.e3.z);
-                const int d = (n0 >= n1 && n0 >= n2) ? 0 : (n1 >= n2 ? 1 : 2);
-                const int ia = d == 0 ? 1 : 0;
-                const int ib = d == 2 ? 1 : 2;
-                const float nd = sel3(d, o.e3.x, o.e3.y, o.e3.z);
-                const float na = sel3(ia, o.e3.x, o.e3.y, o.e3.z);
-                const float nb = sel3(ib, o.e3.x, o.e3.y, o.e3.z);
-                const int D0 = sel3i(d, X0, Y0, Z0);
-                const int A0 = sel3i(ia, X0, Y0, Z0);
-                const int B0 = sel3i(ib, X0, Y0, Z0);
-                const int sd = sel3i(d, 1, TE, TE * TE);
-                const int sa = sel3i(ia, 1, TE, TE * TE);
-                const int sb = sel3i(ib, 1, TE, TE * TE);
-                const int ca = lane & (TE - 1), cb = lane >> 3;
-                const int va = A0 + ca, vb = B0 + cb;
-                // every axis ends at +h; the x axis starts at 0, y and z at -h
-                const bool col_in = va <= g.h && vb <= g.h;
-                const float q = fmaf(na, static_cast<float>(va), nb * static_cast<float>(vb));
-                const float inv = 1.0f / nd;
-                const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
-                const int lo = max(static_cast<int>(ceilf(fminf(t1, t2))), D0);
-                const int hi = min(static_cast<int>(floorf(fmaxf(t1, t2))), min(D0 + TE - 1, g.h));
-                const int cnt = col_in ? max(hi - lo + 1, 0) : 0;
-                int incl = cnt;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int y = __shfl_up(incl, off);
-                    if (lane >= off) incl += y;
-                }
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(incl, off);
+                if (lane >= off) incl += y;
+            }
+            const int H = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+            if (H > 0) {
                 const int excl = incl - cnt;
-                const int H = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
                 const int lid0 = ca * sa + cb * sb + (lo - D0) * sd;
                 for (int k = 0; k < cnt; ++k) list[excl + k] = static_cast<unsigned short>(lid0 + k * sd);
-                wave_sync();
+                // 2. the staged samples of this slice go to LDS
+                commit();
+            }
+            // next slice's loads are issued before this slice's windows
+            Stage nxt = cur;
+            const int s_next = next_slice();
+            if (s_next >= 0) issue(s_next, nxt);
+            wave_sync();
 
+            if (H > 0) {
                 // 3. windows of the hits, 64 per round
+                const float fkx_lo = static_cast<float>(cur.kx_lo), fky_lo = static_cast<float>(cur.ky_lo);
                 for (int r = 0; r < H; r += 64) {
                     const int hh = r + lane;
                     if (hh < H) {
@@ -272,17 +398,25 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
                         const float vx = static_cast<float>(X0 + (lid & 7));
                         const float vy = static_cast<float>(Y0 + ((lid >> 3) & 7));
                         const float vz = static_cast<float>(Z0 + (lid >> 6));
-                        const float ux = fmaf(o.e1.x, vx, fmaf(o.e1.y, vy, o.e1.z * vz));
-                        const float uy = fmaf(o.e2.x, vx, fmaf(o.e2.y, vy, o.e2.z * vz));
-                        const float uz = fmaf(o.e3.x, vx, fmaf(o.e3.y, vy, o.e3.z * vz));
+                        const float ux = fmaf(cur.e1.x, vx, fmaf(cur.e1.y, vy, cur.e1.z * vz));
+                        const float uy = fmaf(cur.e2.x, vx, fmaf(cur.e2.y, vy, cur.e2.z * vz));
+                        const float uz = fmaf(e3.x, vx, fmaf(e3.y, vy, e3.z * vz));
                         float pr, pi, pw;
-                        if (rim)
-                            window_lds<WIN, true, LERP>(rect, tab, g, tmax, ux, uy, uz, kx_lo, ky_lo, pr, pi, pw);
+                        constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
+                        if (cur.rim)
+                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, pr, pi, pw);
                         else
-                            window_lds<WIN, false, LERP>(rect, tab, g, tmax, ux, uy, uz, kx_lo, ky_lo, pr, pi, pw);
-                        acc_re[lid] += pr;
-                        acc_im[lid] += pi;
-                        acc_w[lid] += pw;
+                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, pr, pi, pw);
+                        // a voxel appears once per slice: single writer within the wave
+                        if (FLAGS & SLAB_ATOMIC) {
+                            atomicAdd(acc_re + lid, pr);
+                            atomicAdd(acc_im + lid, pi);
+                            atomicAdd(acc_w + lid, pw);
+                        } else {
+                            acc_re[lid] += pr;
+                            acc_im[lid] += pi;
+                            acc_w[lid] += pw;
+                        }
                     }
                 }
                 wave_sync();
@@ -301,6 +435,8 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
                     wave_sync();
                 }
             }
+            cur = nxt;
+            s = s_next;
         }
 #pragma unroll
         for (int k = 0; k < TV / 64; ++k) {
@@ -336,15 +472,15 @@ __global__ __launch_bounds__(1024) void k_insert_slab(
     }
 }
 
-template <int WIN, bool LERP>
-hipError_t launch_slab_t(const Geom &g, const float2 *slices, const Orient *orient, int count, const float2 *table,
+template <int WIN, bool LERP, int FLAGS>
+hipError_t launch_slab_t(const Geom &g, const void *slices, const Orient *orient, int count, const float2 *table,
                          const Item *items, int nitems, float4 *partials, int inner_chunk, int blocks, int wpb,
                          Counters *ctr, float2 *G, float *W, hipStream_t st)
 {
     const size_t lds = (static_cast<size_t>(table_words(g.N)) + static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) *
                        sizeof(float);
-    hipLaunchKernelGGL((k_insert_slab<WIN, LERP>), dim3(blocks), dim3(64 * wpb), lds, st, g, slices, orient, count,
-                       table, items, nitems, partials, inner_chunk, ctr, G, W);
+    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS>), dim3(blocks), dim3(64 * wpb), lds, st, g, slices, orient,
+                       count, table, items, nitems, partials, inner_chunk, ctr, G, W);
     return hipGetLastError();
 }
 
@@ -385,24 +521,42 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(Geom g, const Item *__
 size_t slab_lds_bytes(const Geom &g, int waves_per_block)
 {
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
-    const int rect = win + 16;
+    const int rect = win + 17;
     const size_t wave_words = ACC_WORDS + 2 * rect * rect + LIST_WORDS;
     return (static_cast<size_t>(table_words(g.N)) + waves_per_block * wave_words) * sizeof(float);
 }
 
-hipError_t launch_insert_slab(const Geom &g, bool lerp, const float2 *slices, const Orient *orient, int count,
-                              const float2 *table, const Item *items, int nitems, float4 *partials,
+hipError_t launch_insert_slab(const Geom &g, bool lerp, int flags, const void *slices, const Orient *orient,
+                              int count, const float2 *table, const Item *items, int nitems, float4 *partials,
                               int inner_chunk, int blocks, int wpb, Counters *ctr, float2 *G, float *W,
                               hipStream_t st)
 {
     if (count <= 0 || nitems <= 0) return hipSuccess;
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
+    // every flag combination exists for the common window (a in [1.5, 2)) with
+    // linear interpolation; other windows and truncation use the default flags
+    if (win == 4 && lerp) {
+        switch (flags & 3) {
+        case 0:
+            return launch_slab_t<4, true, 0>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
+                                             blocks, wpb, ctr, G, W, st);
+        case 1:
+            return launch_slab_t<4, true, 1>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
+                                             blocks, wpb, ctr, G, W, st);
+        case 2:
+            return launch_slab_t<4, true, 2>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
+                                             blocks, wpb, ctr, G, W, st);
+        default:
+            return launch_slab_t<4, true, 3>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
+                                             blocks, wpb, ctr, G, W, st);
+        }
+    }
 #define RECON_SLAB_CASE(WV)                                                                                   \
     case WV:                                                                                                  \
-        return lerp ? launch_slab_t<WV, true>(g, slices, orient, count, table, items, nitems, partials,      \
-                                              inner_chunk, blocks, wpb, ctr, G, W, st)                        \
-                    : launch_slab_t<WV, false>(g, slices, orient, count, table, items, nitems, partials,     \
-                                               inner_chunk, blocks, wpb, ctr, G, W, st);
+        return lerp ? launch_slab_t<WV, true, SLAB_DEFAULT>(g, slices, orient, count, table, items, nitems,   \
+                                                            partials, inner_chunk, blocks, wpb, ctr, G, W, st) \
+                    : launch_slab_t<WV, false, SLAB_DEFAULT>(g, slices, orient, count, table, items, nitems,  \
+                                                             partials, inner_chunk, blocks, wpb, ctr, G, W, st);
     switch (win) {
         RECON_SLAB_CASE(1)
         RECON_SLAB_CASE(2)

@@ -30,7 +30,18 @@ class recon_params(ctypes.Structure):
 class recon_config(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("inner_chunk", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 11)]
+                ("slab_flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 10)]
+
+
+class recon_tune_opts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("target_ns_per_slice", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+class recon_tune_info(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("steps_done", ctypes.c_int32), ("space_size", ctypes.c_int32),
+                ("best_index", ctypes.c_int32), ("best_ns_per_slice", ctypes.c_double),
+                ("mean_ns_per_slice", ctypes.c_double), ("best", recon_config)]
 
 
 class ReconError(RuntimeError):
@@ -64,6 +75,13 @@ def load_library():
         "recon_get_config": ([vp, P(recon_config)], i32),
         "recon_set_stream": ([vp, vp], i32),
         "recon_set_timing_events": ([vp, vp, vp], i32),
+        "recon_tune_space_size": ([vp, P(i32)], i32),
+        "recon_tune_space_config": ([vp, i32, P(recon_config)], i32),
+        "recon_tune_begin": ([vp, P(recon_tune_opts)], i32),
+        "recon_tune_get_info": ([vp, P(recon_tune_info)], i32),
+        "recon_tune_end": ([vp], i32),
+        "recon_tune_invocations": ([ctypes.c_double] * 4 + [P(ctypes.c_double)], i32),
+        "recon_tune_steps": ([ctypes.c_double] * 2 + [P(ctypes.c_double)], i32),
         "recon_stats": ([vp, P(ctypes.c_uint64), P(ctypes.c_uint64)], i32),
         "recon_destroy": ([vp], None),
         "recon_last_error": ([], ctypes.c_char_p),
@@ -147,6 +165,46 @@ def recon_set_timing_events(ctx, start=None, stop=None):
     _check(load_library().recon_set_timing_events(ctx, sp, tp))
 
 
+def recon_tune_space_size(ctx) -> int:
+    n = ctypes.c_int32()
+    _check(load_library().recon_tune_space_size(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def recon_tune_space_config(ctx, index: int) -> recon_config:
+    c = recon_config()
+    _check(load_library().recon_tune_space_config(ctx, int(index), ctypes.byref(c)))
+    return c
+
+
+def recon_tune_begin(ctx, max_steps: int = 0, seed: int = 0, target_ns_per_slice: float = 0.0):
+    o = recon_tune_opts()
+    o.max_steps, o.seed, o.target_ns_per_slice = int(max_steps), int(seed), float(target_ns_per_slice)
+    _check(load_library().recon_tune_begin(ctx, ctypes.byref(o)))
+
+
+def recon_tune_get_info(ctx) -> recon_tune_info:
+    i = recon_tune_info()
+    _check(load_library().recon_tune_get_info(ctx, ctypes.byref(i)))
+    return i
+
+
+def recon_tune_end(ctx):
+    _check(load_library().recon_tune_end(ctx))
+
+
+def recon_tune_invocations(rp: float, s: float, t_avg: float, t_well: float) -> float:
+    out = ctypes.c_double()
+    _check(load_library().recon_tune_invocations(rp, s, t_avg, t_well, ctypes.byref(out)))
+    return out.value
+
+
+def recon_tune_steps(r: float, p: float) -> float:
+    out = ctypes.c_double()
+    _check(load_library().recon_tune_steps(r, p, ctypes.byref(out)))
+    return out.value
+
+
 def recon_stats(ctx):
     a, b = ctypes.c_uint64(), ctypes.c_uint64()
     _check(load_library().recon_stats(ctx, ctypes.byref(a), ctypes.byref(b)))
@@ -209,8 +267,13 @@ class Reconstruction:
             raise ValueError("slices and quaternions must be on the reconstruction's device")
         if tuple(quats.shape) != (S, 4) or quats.dtype != torch.float32 or not quats.is_contiguous():
             raise ValueError("quats must be a contiguous float32 [S, 4] tensor")
-        if tuple(slices.shape) != (S, n, w) or slices.dtype != torch.complex64 or not slices.is_contiguous():
-            raise ValueError(f"slices must be a contiguous complex64 [S, {n}, {w}] tensor")
+        dt = int(self.params.slice_dtype)
+        want = {RECON_SLICE_C64: (torch.complex64, (S, n, w)), RECON_SLICE_F16: (torch.float16, (S, n, w, 2)),
+                RECON_SLICE_BF16: (torch.bfloat16, (S, n, w, 2))}[dt]
+        if slices.dtype != want[0] or tuple(slices.shape) != want[1] or not slices.is_contiguous():
+            raise ValueError(f"slices must be a contiguous {want[0]} tensor of shape {want[1]}")
+        if dt == RECON_SLICE_F16 and (scales is None or scales.dtype != torch.float32 or scales.shape != (S,)):
+            raise ValueError("half-precision slices need float32 scales of shape [S]")
         mb = int(self.params.max_batch)
         for s0 in range(0, S, mb):
             s1 = min(S, s0 + mb)

@@ -210,3 +210,46 @@ def make_workload(name: str = "small", n: int | None = None, S: int | None = Non
     slices = make_slices(ph, quats.astype(np.float64), n)
     return Workload(name=name, n=n, slices=slices, quats=quats, phantom=ph,
                     meta=dict(K=K, seed_phantom=sp, seed_orient=so, clustered=cl))
+
+
+# --------------------------------------------------------------------------
+# 16-bit slice storage (the storage formats the library accepts)
+# --------------------------------------------------------------------------
+def _f32_to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Round FP32 to bfloat16 (round to nearest, ties to even); returns uint16 bits."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    lsb = (b >> 16) & 1
+    rounded = b + np.uint32(0x7FFF) + lsb
+    return (rounded >> 16).astype(np.uint16)
+
+
+def quantize_slices(slices: np.ndarray, fmt: str):
+    """Store complex64 slices as 16-bit (re, im) pairs.
+
+    fmt = "f16": IEEE half values of F / scale_s with one FP32 scale per slice,
+    chosen as max(|re|, |im|) / 32768 (so the largest component maps to 32768,
+    well inside the half range); fmt = "bf16": bfloat16 values, scale 1.
+    Returns (bits uint16 [S][n][n/2+1][2], scales float32 [S])."""
+    sl = np.ascontiguousarray(slices, dtype=np.complex64)
+    S = sl.shape[0]
+    comp = sl.view(np.float32).reshape(sl.shape + (2,))
+    if fmt == "f16":
+        peak = np.abs(comp).reshape(S, -1).max(axis=1)
+        scales = np.where(peak > 0, peak / 32768.0, 1.0).astype(np.float32)
+        q = (comp / scales[:, None, None, None]).astype(np.float16)
+        return q.view(np.uint16), scales
+    if fmt == "bf16":
+        return _f32_to_bf16_bits(comp), np.ones(S, dtype=np.float32)
+    raise ValueError("fmt must be 'f16' or 'bf16'")
+
+
+def dequantize_slices(bits: np.ndarray, scales: np.ndarray, fmt: str) -> np.ndarray:
+    """Exact complex64 values of 16-bit stored slices (what the kernels read)."""
+    if fmt == "f16":
+        comp = bits.view(np.float16).astype(np.float32) * scales[:, None, None, None].astype(np.float32)
+    elif fmt == "bf16":
+        comp = (bits.astype(np.uint32) << 16).view(np.float32)
+    else:
+        raise ValueError("fmt must be 'f16' or 'bf16'")
+    comp = np.ascontiguousarray(comp, dtype=np.float32)
+    return comp.view(np.complex64).reshape(bits.shape[:-1])

@@ -53,7 +53,7 @@ def test_default_params_and_sizes(recon):
 @pytest.mark.parametrize("field,value", [
     ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 3.5),
     ("blob_alpha", -1.0), ("blob_order", 9), ("table_size", 1), ("table_lerp", 2),
-    ("r_max", 64.5), ("r_max", 0.0), ("max_batch", 0), ("slice_dtype", 7),
+    ("r_max", 64.5), ("r_max", 0.0), ("max_batch", 0), ("slice_dtype", 7), ("slice_dtype", -1),
 ])
 def test_invalid_params_rejected(recon, field, value):
     p = recon.recon_default_params(128)
