@@ -37,7 +37,12 @@ WORKLOAD_TEXT = {
              "batches of 1,500 slices",
     "small": "small insertion: 500 Fourier slices of 64x64 (half plane 64x33 complex64) into a 65^3 "
              "complex64 G + float32 W, KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp)",
+    "batch8": "batched insertion: 8 reconstructions, boxes 64,96,128,160,192,224,256,256, slice counts "
+              "uniform in 2,000-20,000 (seed 5), FP32, one persistent slab launch per round of batches "
+              "of up to 1,500 slices per reconstruction",
 }
+BATCH8_N = (64, 96, 128, 160, 192, 224, 256, 256)
+MEAN_FOOTPRINT = 28.737   # mean voxels within a = 1.9 of a random point (estimate for the batch workload)
 
 
 def kernel_sha() -> str:
@@ -96,6 +101,8 @@ def main(argv=None):
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the insertion shards by slices, see DESIGN.md)", file=sys.stderr)
         return 2
+    if args.workload == "batch8":
+        return bench_batch8(args)
 
     import numpy as np
     import torch
@@ -227,6 +234,79 @@ def main(argv=None):
     }
     print(json.dumps(result), flush=True)
     rec.close()
+    return 0
+
+
+def disk_samples(n: int) -> int:
+    h = n // 2
+    k = range(-h, h + 1)
+    return sum(1 for kx in k for ky in k if kx * kx + ky * ky < h * h)
+
+
+def bench_batch8(args) -> int:
+    """Eight reconstructions of different sizes inserted by one persistent
+    launch per round (recon_batch_insert).  Slices are random complex samples
+    generated on the device (the cost depends on geometry, not on values);
+    pair counts are estimated as slices x disk samples x mean footprint."""
+    import numpy as np
+    import torch
+
+    from paper_1910_08498_amd import recon
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    counts = [int(c) for c in rng.integers(2000, 20001, size=len(BATCH8_N))]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    jobs = []
+    for n, S in zip(BATCH8_N, counts):
+        h = n // 2
+        sl = torch.view_as_complex(torch.randn((S, n, h + 1, 2), generator=gen, device=dev)).contiguous()
+        q = torch.randn((S, 4), generator=gen, device=dev)
+        rec = recon.Reconstruction(n, device=dev, max_batch=args.batch)
+        jobs.append((n, S, sl, q, rec))
+        print(f"bench: job n={n} S={S}", file=sys.stderr, flush=True)
+    ctxs = [j[4].ctx for j in jobs]
+    ws = torch.empty(recon.recon_batch_query_size(ctxs), dtype=torch.uint8, device=dev)
+    b = recon.recon_batch_create(ctxs, ws)
+    rounds = max((S + args.batch - 1) // args.batch for _, S, _, _, _ in jobs)
+
+    def step():
+        for j in jobs:
+            j[4].reset()
+        for r in range(rounds):
+            sls, qts, cnt = [], [], []
+            for n, S, sl, q, rec in jobs:
+                s0, s1 = min(S, r * args.batch), min(S, (r + 1) * args.batch)
+                sls.append(sl[s0:s1] if s1 > s0 else None)
+                qts.append(q[s0:s1] if s1 > s0 else None)
+                cnt.append(s1 - s0)
+            recon.recon_batch_insert(b, sls, None, qts, cnt)
+        for j in jobs:
+            j[4].finalize()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    U = sum(S * disk_samples(n) * MEAN_FOOTPRINT for n, S, _, _, _ in jobs)
+    result = {
+        "metric": "slice-sample×voxel updates/s", "value": U / (ms / 1e3), "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: random complex slice samples and orientations generated on the device",
+        "config": {"workload": WORKLOAD_TEXT["batch8"], "boxes": list(BATCH8_N), "slices": counts,
+                   "rounds_per_step": rounds, "pairs_estimated": U},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+    recon.recon_batch_destroy(b)
+    for j in jobs:
+        j[4].close()
     return 0
 
 

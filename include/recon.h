@@ -155,6 +155,36 @@ recon_status recon_set_stream(recon_ctx *ctx, void *stream);
 recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
 
 /* ---------------------------------------------------------------------
+ * Batched insertion: several reconstructions (up to 8, any box sizes and
+ * slice counts, same blob parameters, same device) inserted by one
+ * persistent launch of the slab kernel, whose work queue holds the tiles of
+ * every reconstruction ordered by estimated cost.  recon_batch_insert only
+ * enqueues kernels (no host synchronisation, no allocation, no copies), so a
+ * caller may capture it in a HIP graph and replay it.  Work runs on the
+ * first context's stream.
+ * --------------------------------------------------------------------- */
+typedef struct recon_batch recon_batch;
+
+/* Device workspace bytes the batch needs (its combined work plan). */
+recon_status recon_batch_query_size(recon_ctx *const *ctxs, int32_t njobs, size_t *ws_bytes);
+
+/* Builds the combined plan for the contexts and uploads it into d_ws
+ * (256-byte aligned, at least the queried size; synchronises the first
+ * context's stream once).  The contexts must outlive the batch. */
+recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_ws, size_t ws_bytes,
+                                 recon_batch **out);
+
+/* Inserts counts[j] slices into reconstruction j, for every j, in one
+ * launch.  Per job: d_slices[j] (the context's slice storage type),
+ * d_scales[j] (half storage only, else may be NULL; the array itself may be
+ * NULL when no job needs scales), d_quats[j]; 0 <= counts[j] <= that
+ * context's max_batch. */
+recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, const float *const *d_scales,
+                                const float *const *d_quats, const int32_t *counts);
+
+void recon_batch_destroy(recon_batch *b);
+
+/* ---------------------------------------------------------------------
  * Dynamic autotuning (Sect. 3.2, "Offline and Dynamic tuning", and its use
  * in Sect. 5.3: non-blocking tuning, where every tuning step performs real
  * work with a new configuration, here one recon_insert_batch call, and the
@@ -207,6 +237,31 @@ recon_status recon_tune_end(recon_ctx *ctx);
  * well-performing configurations with probability p: s = log(1-p) / log(1-r). */
 recon_status recon_tune_invocations(double rp, double s, double t_avg, double t_well, double *n);
 recon_status recon_tune_steps(double r, double p, double *s);
+
+/* ---------------------------------------------------------------------
+ * Learned configuration predictor: a multilayer perceptron
+ * n_in -> n_hidden -> n_hidden -> n_out (ReLU, softmax) mapping workload
+ * features to scores over the tuning space, trained on the tuner's timings.
+ * The paper names learning from collected tuning data as related and future
+ * work (Sect. 2; Sect. 6).  Parameters are one device float buffer
+ * W1[n_in][H], b1[H], W2[H][H], b2[H], W3[H][C], b3[C] (row-major, [in][out]).
+ * Sizes: 1 <= n_in <= 64, 1 <= H <= 1024, 2 <= C <= 4096, 1 <= batch <= 65536.
+ * --------------------------------------------------------------------- */
+recon_status recon_mlp_sizes(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch,
+                             size_t *param_floats, size_t *ws_bytes);
+
+/* Inference: d_probs[batch][n_out] = softmax(MLP(d_x[batch][n_in])).
+ * d_ws: device workspace of ws_bytes from recon_mlp_sizes. Asynchronous on `stream`. */
+recon_status recon_mlp_forward(const float *d_params, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                               const float *d_x, int32_t batch, void *d_ws, float *d_probs, void *stream);
+
+/* One gradient-descent step on the mean cross-entropy against target
+ * distributions d_y[batch][n_out]: d_params -= lr * gradient.  Optional
+ * outputs: d_loss (one float, the batch loss before the step) and d_grads
+ * (the gradient, parameter layout).  lr = 0 only computes them. */
+recon_status recon_mlp_train_step(float *d_params, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                                  const float *d_x, const float *d_y, int32_t batch, float lr,
+                                  void *d_ws, float *d_loss, float *d_grads, void *stream);
 
 /* Slices inserted so far and slices rejected for a bad quaternion.
  * Synchronises the context's stream. */

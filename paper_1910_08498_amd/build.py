@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librecon.so")
-SOURCES = ["kernels.hip", "slab.hip", "recon_api.cpp"]
+SOURCES = ["kernels.hip", "slab.hip", "mlp.hip", "recon_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

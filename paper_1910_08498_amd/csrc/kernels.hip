@@ -107,11 +107,11 @@ hipError_t launch_zero(float *p, size_t count, hipStream_t st)
 // orientation prep: quaternion (w, x, y, z) -> columns of R, in FP32
 // ---------------------------------------------------------------------------
 __global__ void k_prep(const float4 *__restrict__ quats, int count, Orient *__restrict__ orient,
-                       Counters *__restrict__ ctr)
+                       Counters *__restrict__ ctr, unsigned *__restrict__ queue)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
-        ctr->queue = 0u;
+        if (queue) *queue = 0u;
         atomicAdd(&ctr->inserted, static_cast<unsigned long long>(count));
     }
     if (s >= count) return;
@@ -137,11 +137,12 @@ __global__ void k_prep(const float4 *__restrict__ quats, int count, Orient *__re
     orient[s] = o;
 }
 
-hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr, hipStream_t st)
+hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr, unsigned *queue,
+                       hipStream_t st)
 {
     const int blocks = count > 0 ? (count + 255) / 256 : 1;
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st,
-                       reinterpret_cast<const float4 *>(quats), count, orient, ctr);
+                       reinterpret_cast<const float4 *>(quats), count, orient, ctr, queue);
     return hipGetLastError();
 }
 

@@ -55,17 +55,37 @@ struct Counters {
     unsigned int pad[59];
 };
 
-// Work item of the binned kernel: one 4x4x4 voxel tile and one slice range.
+// Work item of the queue kernels: one voxel tile and one slice range.
 struct Item {
-    int tile;      // tile index (tx + TX * (ty + TY * tz))
+    int tile;      // tile index (tx + TX * (ty + TY * tz)); slab kernel: job id in bits 24..31
     int part;      // k-th of nparts slice ranges
     int nparts;    // number of ranges the tile's slices are split into
     int slot;      // partial-sum slot (when nparts > 1), else -1
 };
 
+// One reconstruction of a slab launch.  Several reconstructions (jobs) with
+// the same blob parameters can share one persistent launch.
+constexpr int kMaxJobs = 8;
+struct JobDesc {
+    Geom g;
+    const void *slices;      // this batch's stored slices
+    const Orient *orient;    // orientation records of this batch
+    float4 *partials;        // partial-sum slots of split tiles
+    float2 *G;
+    float *W;
+    int count;               // slices in this batch
+    int pad;
+};
+struct JobTable {
+    JobDesc job[kMaxJobs];
+    int njobs;
+};
+
 // Host launchers (defined in kernels.hip).
 hipError_t launch_zero(float *p, size_t count, hipStream_t st);
-hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr,
+// Orientation records for a batch; adds `count` to ctr->inserted; zeroes
+// *queue (a work-queue head) when given.
+hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr, unsigned *queue,
                        hipStream_t st);
 hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices,
                                const Orient *orient, int count, const float2 *table,
@@ -81,13 +101,19 @@ hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   hipStream_t st);
 // Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
 size_t slab_lds_bytes(const Geom &g, int waves_per_block);
-hipError_t launch_insert_slab(const Geom &g, bool lerp, int flags, const void *slices, const Orient *orient,
-                              int count, const float2 *table, const Item *items, int nitems,
-                              float4 *partials, int inner_chunk, int blocks, int waves_per_block,
-                              Counters *ctr, float2 *G, float *W, hipStream_t st);
-hipError_t launch_reduce_partials8(const Geom &g, const Item *items, int nitems,
-                                   const float4 *partials, float2 *G, float *W, hipStream_t st);
+hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
+                              int nitems, int inner_chunk, int blocks, int waves_per_block, Counters *ctr,
+                              hipStream_t st);
+hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st);
 hipError_t launch_finalize(const Geom &g, float2 *G, float *W, float2 *V, float thr,
                            hipStream_t st);
+
+// Learned configuration predictor (mlp.hip).
+size_t mlp_param_count(int n_in, int H, int C);
+size_t mlp_ws_floats(int n_in, int H, int C, int B);
+hipError_t mlp_forward(const float *params, int n_in, int H, int C, const float *x, int B, float *ws, float *probs,
+                       hipStream_t st);
+hipError_t mlp_train_step(float *params, int n_in, int H, int C, const float *x, const float *y, int B, float lr,
+                          float *ws, float *loss, float *grads_out, hipStream_t st);
 
 }  // namespace recon

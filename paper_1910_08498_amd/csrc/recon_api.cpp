@@ -447,7 +447,7 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     Orient *orient = reinterpret_cast<Orient *>(c->ws + c->L.orient);
     const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
     const void *slices = d_slices;
-    hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, c->stream);
+    hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, &ctr->queue, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
     if (c->ev_start) {
         e = hipEventRecord(c->ev_start, c->stream);
@@ -476,12 +476,14 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     const int nitems = static_cast<int>(c->plan.items.size());
     const int blocks = c->num_cu;
     const bool slab = c->cfg.variant == RECON_VARIANT_SLAB;
-    if (slab)
-        e = recon::launch_insert_slab(c->g, c->p.table_lerp != 0, c->cfg.slab_flags & 3, slices, orient, count, table,
-                                      items, nitems,
-                                      partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G, c->W,
-                                      c->stream);
-    else
+    recon::JobTable jt;
+    if (slab) {
+        std::memset(&jt, 0, sizeof(jt));
+        jt.njobs = 1;
+        jt.job[0] = {c->g, slices, orient, partials, c->G, c->W, count, 0};
+        e = recon::launch_insert_slab(jt, c->p.table_lerp != 0, c->cfg.slab_flags & 3, table, items, nitems,
+                                      c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->stream);
+    } else
         e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
                                         partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
                                         c->W, c->stream);
@@ -495,7 +497,7 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
         if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
     }
     if (c->plan.nslots > 0) {
-        e = slab ? recon::launch_reduce_partials8(c->g, items, nitems, partials, c->G, c->W, c->stream)
+        e = slab ? recon::launch_reduce_partials8(jt, items, nitems, c->stream)
                  : recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
     }
@@ -767,6 +769,187 @@ recon_status recon_stats(recon_ctx *c, uint64_t *inserted, uint64_t *rejected)
     if (e != hipSuccess) return hip_fail(e, "recon_stats");
     if (inserted) *inserted = h.inserted;
     if (rejected) *rejected = h.rejected;
+    return RECON_OK;
+}
+
+}  // extern "C"
+
+struct recon_batch {
+    std::vector<recon_ctx *> ctxs;
+    unsigned char *ws;
+    size_t ws_bytes;
+    int nitems;
+    size_t off_items;
+};
+
+// Combined work plan of a batch: every context's slab plan (split 32),
+// tagged with its job index in the tile field's top byte, in decreasing
+// estimated cost across all jobs.
+static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vector<Item> *items)
+{
+    if (!ctxs || njobs < 1 || njobs > recon::kMaxJobs)
+        return fail(RECON_EINVAL, "a batch holds 1 to %d contexts", recon::kMaxJobs);
+    for (int j = 0; j < njobs; ++j) {
+        if (!ctxs[j]) return fail(RECON_EINVAL, "context %d is NULL", j);
+        const recon_params &p = ctxs[j]->p, &q = ctxs[0]->p;
+        if (p.blob_radius != q.blob_radius || p.blob_alpha != q.blob_alpha || p.blob_order != q.blob_order ||
+            p.table_size != q.table_size || p.table_lerp != q.table_lerp)
+            return fail(RECON_EINVAL, "batched contexts must share blob parameters (context %d differs)", j);
+        if (ctxs[j]->device != ctxs[0]->device) return fail(RECON_EINVAL, "batched contexts must share a device");
+        for (int k = 0; k < j; ++k)
+            if (ctxs[k] == ctxs[j]) return fail(RECON_EINVAL, "context %d appears twice", j);
+    }
+    struct Tmp { Item it; double cost; };
+    std::vector<Tmp> all;
+    for (int j = 0; j < njobs; ++j) {
+        const Plan pl = make_plan(ctxs[j]->p, 32, 8);
+        // the plan is sorted by cost already; recompute a comparable cost as
+        // (slice visits) for interleaving jobs: position-weighted by max_batch
+        const size_t n = pl.items.size();
+        for (size_t i = 0; i < n; ++i) {
+            Item it = pl.items[i];
+            if (it.tile >= (1 << 24)) return fail(RECON_EINVAL, "box too large for a batch");
+            it.tile |= j << 24;
+            const double cost = static_cast<double>(ctxs[j]->p.max_batch) / it.nparts *
+                                (1.0 - 0.5 * static_cast<double>(i) / std::max<size_t>(n, 1));
+            all.push_back({it, cost});
+        }
+    }
+    std::stable_sort(all.begin(), all.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
+    items->clear();
+    for (const Tmp &t : all) items->push_back(t.it);
+    return RECON_OK;
+}
+
+extern "C" {
+
+recon_status recon_batch_query_size(recon_ctx *const *ctxs, int32_t njobs, size_t *ws_bytes)
+{
+    if (!ws_bytes) return fail(RECON_EINVAL, "ws_bytes is NULL");
+    std::vector<Item> items;
+    recon_status st = batch_plan(ctxs, njobs, &items);
+    if (st != RECON_OK) return st;
+    *ws_bytes = align_up(sizeof(Counters), 256) + align_up(items.size() * sizeof(Item), 256);
+    return RECON_OK;
+}
+
+recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_ws, size_t ws_bytes, recon_batch **out)
+{
+    if (!out) return fail(RECON_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::vector<Item> items;
+    recon_status st = batch_plan(ctxs, njobs, &items);
+    if (st != RECON_OK) return st;
+    const size_t need = align_up(sizeof(Counters), 256) + align_up(items.size() * sizeof(Item), 256);
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return fail(RECON_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(RECON_ENOMEM, "batch workspace too small: %zu given, %zu needed", ws_bytes, need);
+    for (int j = 0; j < njobs; ++j)
+        if (recon::slab_lds_bytes(ctxs[j]->g, 8) > ctxs[j]->max_lds)
+            return fail(RECON_ECONFIG, "the slab kernel does not fit this device for context %d", j);
+    recon_batch *b = new (std::nothrow) recon_batch();
+    if (!b) return fail(RECON_ENOMEM, "host allocation failed");
+    b->ctxs.assign(ctxs, ctxs + njobs);
+    b->ws = static_cast<unsigned char *>(d_ws);
+    b->ws_bytes = ws_bytes;
+    b->nitems = static_cast<int>(items.size());
+    b->off_items = align_up(sizeof(Counters), 256);
+    hipStream_t st0 = ctxs[0]->stream;
+    hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpyAsync(b->ws + b->off_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, st0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st0);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "upload batch plan");
+    }
+    *out = b;
+    return RECON_OK;
+}
+
+recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, const float *const *d_scales,
+                                const float *const *d_quats, const int32_t *counts)
+{
+    if (!b || !d_slices || !d_quats || !counts) return fail(RECON_EINVAL, "NULL argument");
+    const int nj = static_cast<int>(b->ctxs.size());
+    hipStream_t st = b->ctxs[0]->stream;
+    recon::JobTable jt;
+    std::memset(&jt, 0, sizeof(jt));
+    jt.njobs = nj;
+    for (int j = 0; j < nj; ++j) {
+        recon_ctx *c = b->ctxs[j];
+        if (counts[j] < 0 || counts[j] > c->p.max_batch)
+            return fail(RECON_EINVAL, "counts[%d] = %d outside [0, %d]", j, counts[j], c->p.max_batch);
+        if (counts[j] > 0 && (!d_slices[j] || !d_quats[j])) return fail(RECON_EINVAL, "job %d: NULL buffers", j);
+        const float *sc = d_scales ? d_scales[j] : nullptr;
+        if (counts[j] > 0 && c->p.slice_dtype == RECON_SLICE_F16 && !sc)
+            return fail(RECON_EINVAL, "job %d: half-precision slices need scales", j);
+        recon::Geom g = c->g;
+        g.scales = c->p.slice_dtype == RECON_SLICE_F16 ? sc : nullptr;
+        jt.job[j] = {g, d_slices[j], reinterpret_cast<const Orient *>(c->ws + c->L.orient),
+                     reinterpret_cast<float4 *>(c->ws + c->L.partials), c->G, c->W, counts[j], 0};
+    }
+    Counters *bctr = reinterpret_cast<Counters *>(b->ws);
+    for (int j = 0; j < nj; ++j) {
+        recon_ctx *c = b->ctxs[j];
+        if (counts[j] == 0 && j != 0) continue;
+        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j],
+                                          reinterpret_cast<Orient *>(c->ws + c->L.orient),
+                                          reinterpret_cast<Counters *>(c->ws + c->L.ctr),
+                                          j == 0 ? &bctr->queue : nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "batch prep launch");
+    }
+    const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
+    recon_ctx *c0 = b->ctxs[0];
+    const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
+    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, 2, table, items, b->nitems, 32, c0->num_cu, 8,
+                                             bctr, st);
+    if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items, b->nitems, st);
+    if (e != hipSuccess) return hip_fail(e, "batch insert launch");
+    return RECON_OK;
+}
+
+void recon_batch_destroy(recon_batch *b) { delete b; }
+
+static recon_status mlp_check(int32_t n_in, int32_t H, int32_t C, int32_t B)
+{
+    if (n_in < 1 || n_in > 64 || H < 1 || H > 1024 || C < 2 || C > 4096 || B < 1 || B > 65536)
+        return fail(RECON_EINVAL, "MLP sizes out of range (n_in %d, hidden %d, out %d, batch %d)", n_in, H, C, B);
+    return RECON_OK;
+}
+
+recon_status recon_mlp_sizes(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch, size_t *param_floats,
+                             size_t *ws_bytes)
+{
+    recon_status st = mlp_check(n_in, n_hidden, n_out, batch);
+    if (st != RECON_OK) return st;
+    if (param_floats) *param_floats = recon::mlp_param_count(n_in, n_hidden, n_out);
+    if (ws_bytes) *ws_bytes = recon::mlp_ws_floats(n_in, n_hidden, n_out, batch) * sizeof(float);
+    return RECON_OK;
+}
+
+recon_status recon_mlp_forward(const float *d_params, int32_t n_in, int32_t n_hidden, int32_t n_out, const float *d_x,
+                               int32_t batch, void *d_ws, float *d_probs, void *stream)
+{
+    recon_status st = mlp_check(n_in, n_hidden, n_out, batch);
+    if (st != RECON_OK) return st;
+    if (!d_params || !d_x || !d_ws || !d_probs) return fail(RECON_EINVAL, "NULL device buffer");
+    hipError_t e = recon::mlp_forward(d_params, n_in, n_hidden, n_out, d_x, batch, static_cast<float *>(d_ws), d_probs,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "MLP forward launch");
+    return RECON_OK;
+}
+
+recon_status recon_mlp_train_step(float *d_params, int32_t n_in, int32_t n_hidden, int32_t n_out, const float *d_x,
+                                  const float *d_y, int32_t batch, float lr, void *d_ws, float *d_loss,
+                                  float *d_grads, void *stream)
+{
+    recon_status st = mlp_check(n_in, n_hidden, n_out, batch);
+    if (st != RECON_OK) return st;
+    if (!d_params || !d_x || !d_y || !d_ws) return fail(RECON_EINVAL, "NULL device buffer");
+    if (!std::isfinite(lr)) return fail(RECON_EINVAL, "learning rate must be finite");
+    hipError_t e = recon::mlp_train_step(d_params, n_in, n_hidden, n_out, d_x, d_y, batch, lr,
+                                         static_cast<float *>(d_ws), d_loss, d_grads, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "MLP training step launch");
     return RECON_OK;
 }
 

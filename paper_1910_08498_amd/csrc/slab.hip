@@ -164,45 +164,39 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
 // Variant flags of the slab kernel (tuning knobs).
 constexpr int SLAB_ATOMIC = 1;    // LDS float atomics for the accumulators (else read-add-write)
 constexpr int SLAB_PRELOAD = 2;   // issue all window reads before use
-constexpr int SLAB_DEFAULT = SLAB_PRELOAD;
+// windows of 5x5 and more keep too many reads in flight; they interleave
+template <int WIN>
+constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 
 template <int WIN, bool LERP, int FLAGS>
-__global__ __launch_bounds__(512) void k_insert_slab(
-    Geom g, const void *__restrict__ slices, const Orient *__restrict__ orient, int count,
-    const float2 *__restrict__ table_g, const Item *__restrict__ items, int nitems,
-    float4 *__restrict__ partials, int inner_chunk, Counters *__restrict__ ctr,
-    float2 *__restrict__ G, float *__restrict__ W)
+__global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
+                                                     const Item *__restrict__ items, int nitems, int inner_chunk,
+                                                     Counters *__restrict__ ctr)
 {
     using SS = SlabShape<WIN>;
     constexpr int RECT = SS::RECT;
     constexpr int RECT2 = SS::RECT2;
     constexpr int NC = (RECT2 + 63) / 64;
     extern __shared__ float smem[];
+    // blob parameters (and so the table) are common to every job of a launch
+    const int N = jt.job[0].g.N;
     float *tab = smem;
-    for (int i = threadIdx.x; i < g.N; i += blockDim.x) tab[i] = table_g[i].x;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tab[i] = table_g[i].x;
     if (threadIdx.x == 0) {
-        const float sentinel = -1048576.0f * table_g[g.N - 1].x;
-        tab[g.N] = sentinel;
-        tab[g.N + 1] = sentinel;
+        const float sentinel = -1048576.0f * table_g[N - 1].x;
+        tab[N] = sentinel;
+        tab[N + 1] = sentinel;
     }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    float *wregion = smem + table_words(g.N) + wave * SS::WAVE_WORDS;
+    float *wregion = smem + table_words(N) + wave * SS::WAVE_WORDS;
     float *acc_re = wregion;
     float *acc_im = wregion + TV;
     float *acc_w = wregion + 2 * TV;
     float2 *rect = reinterpret_cast<float2 *>(wregion + ACC_WORDS);
     unsigned short *list = reinterpret_cast<unsigned short *>(wregion + ACC_WORDS + 2 * RECT2);
-
-    const int TX = (g.h + 1 + TE - 1) / TE;
-    const int TY = (g.dim + TE - 1) / TE;
-    const size_t slen = static_cast<size_t>(g.n) * g.sw;
-    const float rmax = sqrtf(g.r2max);
-    // voxels with |v| >= r_max + a receive nothing (every sample has |p| < r_max)
-    const float R2 = (rmax + g.a + 1e-3f) * (rmax + g.a + 1e-3f);
-    const float a_run = g.a * (1.0f + 1e-5f) + 1e-5f;
 
     for (;;) {
         unsigned it = 0;
@@ -210,9 +204,26 @@ __global__ __launch_bounds__(512) void k_insert_slab(
         it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
         if (it >= static_cast<unsigned>(nitems)) break;
         const Item item = items[it];
-        const int tx = item.tile % TX;
-        const int ty = (item.tile / TX) % TY;
-        const int tz = item.tile / (TX * TY);
+        // the item's reconstruction (job) and its geometry and buffers
+        const int job = __builtin_amdgcn_readfirstlane(item.tile >> 24);
+        const int tile = item.tile & 0xffffff;
+        const Geom g = jt.job[job].g;
+        const void *__restrict__ slices = jt.job[job].slices;
+        const Orient *__restrict__ orient = jt.job[job].orient;
+        float4 *__restrict__ partials = jt.job[job].partials;
+        float2 *__restrict__ G = jt.job[job].G;
+        float *__restrict__ W = jt.job[job].W;
+        const int count = jt.job[job].count;
+        const int TX = (g.h + 1 + TE - 1) / TE;
+        const int TY = (g.dim + TE - 1) / TE;
+        const size_t slen = static_cast<size_t>(g.n) * g.sw;
+        const float rmax = sqrtf(g.r2max);
+        // voxels with |v| >= r_max + a receive nothing (every sample has |p| < r_max)
+        const float R2 = (rmax + g.a + 1e-3f) * (rmax + g.a + 1e-3f);
+        const float a_run = g.a * (1.0f + 1e-5f) + 1e-5f;
+        const int tx = tile % TX;
+        const int ty = (tile / TX) % TY;
+        const int tz = tile / (TX * TY);
         // voxel box of the tile, clipped to the half box
         const int X0 = TE * tx, Y0 = TE * ty - g.h, Z0 = TE * tz - g.h;
         const int X1 = min(X0 + TE - 1, g.h), Y1 = min(Y0 + TE - 1, g.h), Z1 = min(Z0 + TE - 1, g.h);
@@ -473,30 +484,33 @@ __global__ __launch_bounds__(512) void k_insert_slab(
 }
 
 template <int WIN, bool LERP, int FLAGS>
-hipError_t launch_slab_t(const Geom &g, const void *slices, const Orient *orient, int count, const float2 *table,
-                         const Item *items, int nitems, float4 *partials, int inner_chunk, int blocks, int wpb,
-                         Counters *ctr, float2 *G, float *W, hipStream_t st)
+hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *items, int nitems, int inner_chunk,
+                         int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
-    const size_t lds = (static_cast<size_t>(table_words(g.N)) + static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) *
-                       sizeof(float);
-    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS>), dim3(blocks), dim3(64 * wpb), lds, st, g, slices, orient,
-                       count, table, items, nitems, partials, inner_chunk, ctr, G, W);
+    const size_t lds = (static_cast<size_t>(table_words(jt.job[0].g.N)) +
+                        static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
+    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table, items,
+                       nitems, inner_chunk, ctr);
     return hipGetLastError();
 }
 
 // Adds the partial sums of split 8x8x8 tiles, in part order, into G and W.
-__global__ __launch_bounds__(512) void k_reduce_partials8(Geom g, const Item *__restrict__ items,
-                                                          const float4 *__restrict__ partials,
-                                                          float2 *__restrict__ G, float *__restrict__ W)
+__global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Item *__restrict__ items)
 {
     const Item item = items[blockIdx.x];
     if (item.nparts == 1 || item.part != 0) return;
+    const int job = item.tile >> 24;
+    const int tile = item.tile & 0xffffff;
+    const Geom g = jt.job[job].g;
+    const float4 *__restrict__ partials = jt.job[job].partials;
+    float2 *__restrict__ G = jt.job[job].G;
+    float *__restrict__ W = jt.job[job].W;
     const int lid = threadIdx.x;
     const int TX = (g.h + 1 + TE - 1) / TE;
     const int TY = (g.dim + TE - 1) / TE;
-    const int tx = item.tile % TX;
-    const int ty = (item.tile / TX) % TY;
-    const int tz = item.tile / (TX * TY);
+    const int tx = tile % TX;
+    const int ty = (tile / TX) % TY;
+    const int tz = tile / (TX * TY);
     const int ix = TE * tx + (lid & 7);
     const int iy = TE * ty + ((lid >> 3) & 7);
     const int iz = TE * tz + (lid >> 6);
@@ -526,37 +540,28 @@ size_t slab_lds_bytes(const Geom &g, int waves_per_block)
     return (static_cast<size_t>(table_words(g.N)) + waves_per_block * wave_words) * sizeof(float);
 }
 
-hipError_t launch_insert_slab(const Geom &g, bool lerp, int flags, const void *slices, const Orient *orient,
-                              int count, const float2 *table, const Item *items, int nitems, float4 *partials,
-                              int inner_chunk, int blocks, int wpb, Counters *ctr, float2 *G, float *W,
-                              hipStream_t st)
+hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
+                              int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
-    if (count <= 0 || nitems <= 0) return hipSuccess;
+    if (nitems <= 0) return hipSuccess;
+    const Geom &g = jt.job[0].g;
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
     // every flag combination exists for the common window (a in [1.5, 2)) with
     // linear interpolation; other windows and truncation use the default flags
     if (win == 4 && lerp) {
         switch (flags & 3) {
-        case 0:
-            return launch_slab_t<4, true, 0>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
-                                             blocks, wpb, ctr, G, W, st);
-        case 1:
-            return launch_slab_t<4, true, 1>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
-                                             blocks, wpb, ctr, G, W, st);
-        case 2:
-            return launch_slab_t<4, true, 2>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
-                                             blocks, wpb, ctr, G, W, st);
-        default:
-            return launch_slab_t<4, true, 3>(g, slices, orient, count, table, items, nitems, partials, inner_chunk,
-                                             blocks, wpb, ctr, G, W, st);
+        case 0: return launch_slab_t<4, true, 0>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 1: return launch_slab_t<4, true, 1>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 2: return launch_slab_t<4, true, 2>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        default: return launch_slab_t<4, true, 3>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
         }
     }
-#define RECON_SLAB_CASE(WV)                                                                                   \
-    case WV:                                                                                                  \
-        return lerp ? launch_slab_t<WV, true, SLAB_DEFAULT>(g, slices, orient, count, table, items, nitems,   \
-                                                            partials, inner_chunk, blocks, wpb, ctr, G, W, st) \
-                    : launch_slab_t<WV, false, SLAB_DEFAULT>(g, slices, orient, count, table, items, nitems,  \
-                                                             partials, inner_chunk, blocks, wpb, ctr, G, W, st);
+#define RECON_SLAB_CASE(WV)                                                                                    \
+    case WV:                                                                                                   \
+        return lerp ? launch_slab_t<WV, true, slab_default_flags<WV>()>(jt, table, items, nitems, inner_chunk,  \
+                                                                        blocks, wpb, ctr, st)                  \
+                    : launch_slab_t<WV, false, slab_default_flags<WV>()>(jt, table, items, nitems, inner_chunk, \
+                                                                         blocks, wpb, ctr, st);
     switch (win) {
         RECON_SLAB_CASE(1)
         RECON_SLAB_CASE(2)
@@ -570,11 +575,10 @@ hipError_t launch_insert_slab(const Geom &g, bool lerp, int flags, const void *s
 #undef RECON_SLAB_CASE
 }
 
-hipError_t launch_reduce_partials8(const Geom &g, const Item *items, int nitems, const float4 *partials, float2 *G,
-                                   float *W, hipStream_t st)
+hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials8, dim3(nitems), dim3(TV), 0, st, g, items, partials, G, W);
+    hipLaunchKernelGGL(k_reduce_partials8, dim3(nitems), dim3(TV), 0, st, jt, items);
     return hipGetLastError();
 }
 

@@ -1,0 +1,227 @@
+"""Learned configuration predictor on top of the autotuner (host-side driver).
+
+Everything numeric runs in the library's HIP kernels: the timings come from
+the insertion kernels timed with events, and the predictor is trained and
+evaluated with recon_mlp_train_step / recon_mlp_forward.  This module only
+marshals data: it builds seeded synthetic workloads, collects the time of
+every configuration of the tuning space on each of them, turns timings into
+target distributions, and measures the regret of the predicted configuration
+against the fastest measured one (exhaustive search).
+
+Features of a workload: log2(n), log2(slices), blob radius a.  (The device is
+fixed, so its compute-unit count is not a feature here.)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import recon
+
+N_HIDDEN = 64
+
+
+@dataclass
+class TuneRecord:
+    n: int
+    slices: int
+    a: float
+    ns_per_slice: np.ndarray            # [C] insertion-kernel time per slice of each configuration
+    meta: dict = field(default_factory=dict)
+
+    def features(self) -> np.ndarray:
+        return np.array([math.log2(self.n), math.log2(self.slices), self.a], dtype=np.float64)
+
+
+def sample_workloads(seed: int, count: int, n_range=(48, 384), s_range=(1000, 50000), a_range=(1.5, 2.5)):
+    """Seeded workload parameters: n even (uniform), slices log-uniform, a uniform."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(n_range[0] // 2, n_range[1] // 2 + 1)) * 2
+        s = int(round(math.exp(rng.uniform(math.log(s_range[0]), math.log(s_range[1])))))
+        a = float(rng.uniform(*a_range))
+        out.append((n, s, a))
+    return out
+
+
+def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, device="cuda:0",
+               repeats: int = 1) -> TuneRecord:
+    """Times every configuration of the tuning space on one batch of
+    min(slices, batch_cap) synthetic slices (random complex samples, uniform
+    orientations: the cost depends on the geometry, not the values)."""
+    dev = torch.device(device)
+    count = min(slices, batch_cap)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    h = n // 2
+    sl = torch.randn((count, n, h + 1, 2), generator=g, device=dev, dtype=torch.float32)
+    sl = torch.view_as_complex(sl).contiguous()
+    q = torch.randn((count, 4), generator=g, device=dev, dtype=torch.float32)
+    rec = recon.Reconstruction(n, device=dev, max_batch=count, blob_radius=float(np.float32(a)))
+    size = recon.recon_tune_space_size(rec.ctx)
+    ns = np.zeros(size)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()       # torch creates the events on first record; the library re-records them
+    e1.record()
+    torch.cuda.synchronize()
+    for i in range(size):
+        recon.recon_set_config(rec.ctx, recon.recon_tune_space_config(rec.ctx, i))
+        best = float("inf")
+        for _ in range(repeats + 1):          # first run warms the configuration
+            recon.recon_set_timing_events(rec.ctx, e0, e1)
+            recon.recon_insert_batch(rec.ctx, sl, None, q, count)
+            recon.recon_set_timing_events(rec.ctx, None, None)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        ns[i] = best * 1e6 / count
+    rec.close()
+    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns)
+
+
+def soft_targets(ns: np.ndarray, temperature: float = 0.02) -> np.ndarray:
+    """Target distribution over configurations: softmax of -(t / t_best) / T."""
+    r = -(ns / ns.min(axis=1, keepdims=True)) / temperature
+    r -= r.max(axis=1, keepdims=True)
+    e = np.exp(r)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+class Normalizer:
+    def __init__(self, X: np.ndarray):
+        self.mu = X.mean(axis=0)
+        self.sd = X.std(axis=0) + 1e-9
+
+    def __call__(self, X: np.ndarray) -> np.ndarray:
+        return (X - self.mu) / self.sd
+
+
+class Predictor:
+    """MLP features -> configuration scores, trained with the library's kernels."""
+
+    def __init__(self, n_out: int, seed: int = 0, device="cuda:0"):
+        self.dev = torch.device(device)
+        self.n_in, self.H, self.C = 3, N_HIDDEN, n_out
+        rng = np.random.default_rng(seed)
+        shapes = [(self.n_in, self.H), (self.H,), (self.H, self.H), (self.H,), (self.H, self.C), (self.C,)]
+        parts = []
+        for shp in shapes:
+            if len(shp) == 2:
+                lim = math.sqrt(6.0 / shp[0])
+                parts.append(rng.uniform(-lim, lim, shp).ravel())
+            else:
+                parts.append(np.zeros(shp))
+        self.params = torch.tensor(np.concatenate(parts), dtype=torch.float32, device=self.dev)
+        self.norm = None
+
+    def fit(self, X: np.ndarray, Y: np.ndarray, steps: int = 3000, lr: float = 0.1) -> list:
+        self.norm = Normalizer(X)
+        B = X.shape[0]
+        x = torch.tensor(self.norm(X), dtype=torch.float32, device=self.dev)
+        y = torch.tensor(Y, dtype=torch.float32, device=self.dev)
+        _, wsb = recon.recon_mlp_sizes(self.n_in, self.H, self.C, B)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=self.dev)
+        loss = torch.empty(steps, dtype=torch.float32, device=self.dev)
+        for i in range(steps):
+            recon.recon_mlp_train_step(self.params, self.n_in, self.H, self.C, x, y, B, lr, ws, loss[i:i + 1])
+        return loss.cpu().numpy().tolist()
+
+    def predict(self, X: np.ndarray) -> np.ndarray:
+        B = X.shape[0]
+        x = torch.tensor(self.norm(X), dtype=torch.float32, device=self.dev)
+        _, wsb = recon.recon_mlp_sizes(self.n_in, self.H, self.C, B)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=self.dev)
+        p = torch.empty((B, self.C), dtype=torch.float32, device=self.dev)
+        recon.recon_mlp_forward(self.params, self.n_in, self.H, self.C, x, B, ws, p)
+        return p.cpu().numpy()
+
+
+def regret(ns: np.ndarray, choice: np.ndarray) -> np.ndarray:
+    """Time of the chosen configuration over the fastest, minus one, per workload."""
+    return ns[np.arange(ns.shape[0]), choice] / ns.min(axis=1) - 1.0
+
+
+def random_search_regret(ns: np.ndarray, steps: int, trials: int = 200, seed: int = 0) -> np.ndarray:
+    """Expected regret of the best of `steps` random configurations (the
+    paper's random search with a fixed budget), averaged over trials."""
+    rng = np.random.default_rng(seed)
+    W, C = ns.shape
+    out = np.zeros(W)
+    for _ in range(trials):
+        picks = np.array([rng.choice(C, size=min(steps, C), replace=False) for _ in range(W)])
+        best = ns[np.arange(W)[:, None], picks].min(axis=1)
+        out += best / ns.min(axis=1) - 1.0
+    return out / trials
+
+
+def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temperature: float = 0.02,
+             seed: int = 0, default_index: int | None = None, search_budget: int = 10) -> dict:
+    """Trains on `train` records and reports regrets on `test` records."""
+    Xtr = np.stack([r.features() for r in train])
+    Ytr = soft_targets(np.stack([r.ns_per_slice for r in train]), temperature)
+    Xte = np.stack([r.features() for r in test])
+    NSte = np.stack([r.ns_per_slice for r in test])
+    model = Predictor(Ytr.shape[1], seed=seed)
+    losses = model.fit(Xtr, Ytr, steps=steps, lr=lr)
+    pred = model.predict(Xte).argmax(axis=1)
+    out = {
+        "train_workloads": len(train), "test_workloads": len(test), "configs": int(Ytr.shape[1]),
+        "loss_first": losses[0], "loss_last": losses[-1],
+        "regret_learned_mean": float(regret(NSte, pred).mean()),
+        "regret_learned_max": float(regret(NSte, pred).max()),
+        "regret_random_search_mean": float(random_search_regret(NSte, search_budget, seed=seed).mean()),
+        "random_search_budget": search_budget,
+        "mean_config_over_best": float((NSte.mean(axis=1) / NSte.min(axis=1)).mean()),
+    }
+    if default_index is not None:
+        d = np.full(len(test), default_index)
+        out["regret_default_mean"] = float(regret(NSte, d).mean())
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    import time
+    ap = argparse.ArgumentParser(description="collect tuning data, train and evaluate the learned predictor")
+    ap.add_argument("--train", type=int, default=200)
+    ap.add_argument("--test", type=int, default=50)
+    ap.add_argument("--batch-cap", type=int, default=1000)
+    ap.add_argument("--n-max", type=int, default=384)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    rec0 = recon.Reconstruction(64, device="cuda:0")
+    cur = recon.recon_get_config(rec0.ctx)
+    default_index = None
+    for i in range(recon.recon_tune_space_size(rec0.ctx)):
+        c = recon.recon_tune_space_config(rec0.ctx, i)
+        if (c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags) == \
+                (cur.variant, cur.waves_per_block, cur.inner_chunk, cur.split, cur.slab_flags):
+            default_index = i
+    rec0.close()
+    t0 = time.time()
+    records = []
+    params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
+        sample_workloads(2000, args.test, n_range=(48, args.n_max))
+    for k, (n, s, a) in enumerate(params):
+        records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap))
+        print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} "
+              f"best {records[-1].ns_per_slice.min():.1f} ns/slice ({time.time() - t0:.0f} s)",
+              file=sys.stderr, flush=True)
+    res = evaluate(records[:args.train], records[args.train:], steps=args.steps, default_index=default_index)
+    res["collection_s"] = time.time() - t0
+    res["batch_cap"] = args.batch_cap
+    print(json.dumps(res), flush=True)
+    if args.out:
+        np.savez(args.out, features=np.stack([r.features() for r in records]),
+                 ns=np.stack([r.ns_per_slice for r in records]), n_train=args.train)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

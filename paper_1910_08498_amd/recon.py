@@ -82,6 +82,13 @@ def load_library():
         "recon_tune_end": ([vp], i32),
         "recon_tune_invocations": ([ctypes.c_double] * 4 + [P(ctypes.c_double)], i32),
         "recon_tune_steps": ([ctypes.c_double] * 2 + [P(ctypes.c_double)], i32),
+        "recon_batch_query_size": ([P(vp), i32, P(sz)], i32),
+        "recon_batch_create": ([P(vp), i32, vp, sz, P(vp)], i32),
+        "recon_batch_insert": ([vp, P(vp), P(vp), P(vp), P(i32)], i32),
+        "recon_batch_destroy": ([vp], None),
+        "recon_mlp_sizes": ([i32, i32, i32, i32, P(sz), P(sz)], i32),
+        "recon_mlp_forward": ([vp, i32, i32, i32, vp, i32, vp, vp, vp], i32),
+        "recon_mlp_train_step": ([vp, i32, i32, i32, vp, vp, i32, ctypes.c_float, vp, vp, vp, vp], i32),
         "recon_stats": ([vp, P(ctypes.c_uint64), P(ctypes.c_uint64)], i32),
         "recon_destroy": ([vp], None),
         "recon_last_error": ([], ctypes.c_char_p),
@@ -203,6 +210,56 @@ def recon_tune_steps(r: float, p: float) -> float:
     out = ctypes.c_double()
     _check(load_library().recon_tune_steps(r, p, ctypes.byref(out)))
     return out.value
+
+
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))()
+    for i, c in enumerate(ctxs):
+        arr[i] = c.value if isinstance(c, ctypes.c_void_p) else c
+    return arr
+
+
+def recon_batch_query_size(ctxs) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().recon_batch_query_size(_ctx_array(ctxs), len(ctxs), ctypes.byref(n)))
+    return n.value
+
+
+def recon_batch_create(ctxs, ws):
+    b = ctypes.c_void_p()
+    _check(load_library().recon_batch_create(_ctx_array(ctxs), len(ctxs), _ptr(ws), ws.numel() * ws.element_size(),
+                                             ctypes.byref(b)))
+    return b
+
+
+def recon_batch_insert(batch, slices, scales, quats, counts):
+    """slices, quats: lists of device tensors (or None); scales: list or None."""
+    k = len(counts)
+    sl = (ctypes.c_void_p * k)(*[None if t is None else t.data_ptr() for t in slices])
+    qt = (ctypes.c_void_p * k)(*[None if t is None else t.data_ptr() for t in quats])
+    sc = None if scales is None else (ctypes.c_void_p * k)(*[None if t is None else t.data_ptr() for t in scales])
+    cn = (ctypes.c_int32 * k)(*[int(c) for c in counts])
+    _check(load_library().recon_batch_insert(batch, sl, sc, qt, cn))
+
+
+def recon_batch_destroy(batch):
+    load_library().recon_batch_destroy(batch)
+
+
+def recon_mlp_sizes(n_in: int, n_hidden: int, n_out: int, batch: int):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().recon_mlp_sizes(n_in, n_hidden, n_out, batch, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def recon_mlp_forward(params, n_in, n_hidden, n_out, x, batch, ws, probs, stream=None):
+    _check(load_library().recon_mlp_forward(_ptr(params), n_in, n_hidden, n_out, _ptr(x), batch, _ptr(ws),
+                                            _ptr(probs), _stream(stream)))
+
+
+def recon_mlp_train_step(params, n_in, n_hidden, n_out, x, y, batch, lr, ws, loss=None, grads=None, stream=None):
+    _check(load_library().recon_mlp_train_step(_ptr(params), n_in, n_hidden, n_out, _ptr(x), _ptr(y), batch,
+                                               float(lr), _ptr(ws), _ptr(loss), _ptr(grads), _stream(stream)))
 
 
 def recon_stats(ctx):

@@ -1,0 +1,44 @@
+"""Learned configuration predictor end to end on a reduced problem: timings of
+the whole tuning space on seeded workloads, training with the library's MLP
+kernels, and the regret of the predicted configuration on held-out workloads
+against exhaustive search, the default configuration and random search."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08498_amd import learned, recon
+    return torch, recon, learned
+
+
+def test_learned_predictor_beats_untuned_default(env):
+    torch, recon, learned = env
+    train_p = learned.sample_workloads(11, 14, n_range=(48, 112), s_range=(200, 2000))
+    test_p = learned.sample_workloads(12, 6, n_range=(48, 112), s_range=(200, 2000))
+    recs = []
+    for k, (n, s, a) in enumerate(train_p + test_p):
+        print(f"[gpu] learned timing workload {k} n={n} S={s} a={a:.2f}", flush=True)
+        recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=1))
+    sizes = {r.ns_per_slice.size for r in recs}
+    assert len(sizes) == 1                      # the same tuning space for every workload
+    ns = np.stack([r.ns_per_slice for r in recs])
+    assert np.all(ns > 0)
+    rec0 = recon.Reconstruction(64)
+    cur = recon.recon_get_config(rec0.ctx)
+    default_index = [i for i in range(recon.recon_tune_space_size(rec0.ctx))
+                     if (lambda c: (c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags))(
+                         recon.recon_tune_space_config(rec0.ctx, i)) ==
+                     (cur.variant, cur.waves_per_block, cur.inner_chunk, cur.split, cur.slab_flags)][0]
+    rec0.close()
+    res = learned.evaluate(recs[:14], recs[14:], steps=1500, default_index=default_index)
+    print("   ", res, flush=True)
+    assert res["loss_last"] < res["loss_first"]
+    # picking by prediction costs no tuning steps and stays near the best
+    assert res["regret_learned_mean"] <= res["regret_default_mean"] + 0.02
+    assert res["regret_learned_mean"] < res["mean_config_over_best"] - 1.0
