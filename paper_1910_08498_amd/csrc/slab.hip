@@ -59,6 +59,15 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ float uniformf(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ float4 uniform4(float4 v)
+{
+    return make_float4(uniformf(v.x), uniformf(v.y), uniformf(v.z), uniformf(v.w));
+}
+
 __device__ __forceinline__ float sel3(int i, float x, float y, float z)
 {
     return i == 0 ? x : (i == 1 ? y : z);
@@ -274,13 +283,25 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
         struct Stage {
             float4 e1, e2, e3;
             int kx_lo, ky_lo;
-            bool rim;
+            int rim;          // int, not bool: no padding bytes in the struct copies
+            float scale;
         };
+        // cell[] holds the raw sample words between issue and commit: the
+        // complex64 value, or the packed 16-bit pair in .x.  Decoding waits
+        // for the loads, so it happens at commit, after the previous slice's
+        // windows have hidden their latency.
         float2 cell[NC];
         bool keep[NC];
         int dst[NC];
         auto issue = [&](int s, Stage &st) {
-            const Orient o = orient[s];
+            // s is wave-uniform: the orientation and scale go to scalar
+            // registers here, so no later copy of the stage waits on the
+            // sample loads issued below
+            const Orient ov = orient[s];
+            Orient o;
+            o.e1 = uniform4(ov.e1);
+            o.e2 = uniform4(ov.e2);
+            o.e3 = uniform4(ov.e3);
             st.e1 = o.e1;
             st.e2 = o.e2;
             st.e3 = o.e3;
@@ -296,7 +317,8 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
             const int fym = max(abs(ky_lo), abs(ky_lo + wy - 1));
             st.kx_lo = kx_lo;
             st.ky_lo = ky_lo;
-            st.rim = !(static_cast<float>(fxm * fxm + fym * fym) < g.r2max);
+            st.rim = static_cast<float>(fxm * fxm + fym * fym) < g.r2max ? 0 : 1;
+            st.scale = g.scales ? uniformf(g.scales[s]) : 1.0f;
             const int ncell = wx * wy;
             const float inv_wx = 1.0f / static_cast<float>(wx);
             // buffer resource over this slice: 32-bit offsets, hardware bounds check
@@ -305,7 +327,7 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 const_cast<unsigned char *>(static_cast<const unsigned char *>(slices) +
                                             static_cast<size_t>(s) * slen * eb),
                 static_cast<short>(0), static_cast<int>(slen * eb), 0x00020000);
-            const float sscale = g.scales ? g.scales[s] : 1.0f;
+            int off[NC];
 #pragma unroll
             for (int qq = 0; qq < NC; ++qq) {
                 const int c = qq * 64 + lane;
@@ -318,29 +340,41 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 int col = direct ? kx : -kx;
                 row = valid ? row : g.h;
                 col = valid ? col : 0;
-                const int e = row * g.sw + col;
-                if (g.dtype == 0) {
-                    cell[qq] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, e * 8, 0, 0));
-                } else {
-                    const unsigned raw = __builtin_amdgcn_raw_buffer_load_b32(rs, e * 4, 0, 0);
-                    if (g.dtype == 1) {
-                        const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
-                        const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
-                        cell[qq] = make_float2(static_cast<float>(lo) * sscale, static_cast<float>(hi) * sscale);
-                    } else {
-                        cell[qq] = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
-                    }
-                }
+                off[qq] = (row * g.sw + col) * eb;
                 // the sign flip of mirrored samples is applied at commit
                 keep[qq] = valid;
                 dst[qq] = c < ncell ? (direct ? 1 : -1) * (cy_ * RECT + cx_ + 1) : 0;
             }
+            // all loads back to back (dtype is uniform over the launch)
+            if (g.dtype == 0) {
+#pragma unroll
+                for (int qq = 0; qq < NC; ++qq)
+                    cell[qq] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off[qq], 0, 0));
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < NC; ++qq)
+                    cell[qq].x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off[qq], 0, 0));
+            }
         };
-        auto commit = [&]() {
+        auto commit = [&](const Stage &st) {
+            const int dt = g.dtype;
 #pragma unroll
             for (int qq = 0; qq < NC; ++qq) {
                 if (dst[qq] != 0) {
-                    float2 v = keep[qq] ? cell[qq] : make_float2(0.f, 0.f);
+                    float2 v;
+                    if (dt == 0) {
+                        v = cell[qq];
+                    } else {
+                        const unsigned raw = __float_as_uint(cell[qq].x);
+                        if (dt == 1) {
+                            const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
+                            const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
+                            v = make_float2(static_cast<float>(lo) * st.scale, static_cast<float>(hi) * st.scale);
+                        } else {
+                            v = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
+                        }
+                    }
+                    v = keep[qq] ? v : make_float2(0.f, 0.f);
                     if (dst[qq] < 0) v.y = -v.y;
                     rect[abs(dst[qq]) - 1] = v;
                 }
@@ -391,7 +425,7 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 const int lid0 = ca * sa + cb * sb + (lo - D0) * sd;
                 for (int k = 0; k < cnt; ++k) list[excl + k] = static_cast<unsigned short>(lid0 + k * sd);
                 // 2. the staged samples of this slice go to LDS
-                commit();
+                commit(cur);
             }
             // next slice's loads are issued before this slice's windows
             Stage nxt = cur;
@@ -458,19 +492,30 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
         }
         wave_sync();
         if (item.nparts == 1) {
+            // all reads first, then all writes: G and W may not be proven
+            // disjoint, and interleaving would serialise every read
+            float2 gv[TV / 64];
+            float wv[TV / 64];
+            size_t vi[TV / 64];
+            bool in[TV / 64];
 #pragma unroll
             for (int k = 0; k < TV / 64; ++k) {
                 const int lid = lane + 64 * k;
                 const int ix = X0 + (lid & 7);
                 const int iy = Y0 + ((lid >> 3) & 7) + g.h;
                 const int iz = Z0 + (lid >> 6) + g.h;
-                if (ix <= g.h && iy < g.dim && iz < g.dim) {
-                    const size_t vi = (static_cast<size_t>(iz) * g.dim + iy) * g.dim + (ix + g.h);
-                    float2 gv = G[vi];
-                    gv.x += ore[k];
-                    gv.y += oim[k];
-                    G[vi] = gv;
-                    W[vi] += ow[k];
+                in[k] = ix <= g.h && iy < g.dim && iz < g.dim;
+                vi[k] = (static_cast<size_t>(iz) * g.dim + iy) * g.dim + (ix + g.h);
+                if (in[k]) {
+                    gv[k] = G[vi[k]];
+                    wv[k] = W[vi[k]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TV / 64; ++k) {
+                if (in[k]) {
+                    G[vi[k]] = make_float2(gv[k].x + ore[k], gv[k].y + oim[k]);
+                    W[vi[k]] = wv[k] + ow[k];
                 }
             }
         } else {
