@@ -37,6 +37,9 @@ WORKLOAD_TEXT = {
              "batches of 1,500 slices",
     "small": "small insertion: 500 Fourier slices of 64x64 (half plane 64x33 complex64) into a 65^3 "
              "complex64 G + float32 W, KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp)",
+    "precision": "large insertion with 16-bit slice storage: 50,000 Fourier slices of 256x256 (half plane "
+                 "256x129, 45,000 Haar-uniform + 5,000 clustered views) into a 257^3 complex64 G + float32 W, "
+                 "KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp), batches of 1,500 slices",
     "batch8": "batched insertion: 8 reconstructions, boxes 64,96,128,160,192,224,256,256, slice counts "
               "uniform in 2,000-20,000 (seed 5), FP32, one persistent slab launch per round of batches "
               "of up to 1,500 slices per reconstruction",
@@ -66,11 +69,11 @@ def load_traffic(launch_count_per_step):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(workload, n_slices: int):
+def cpu_baseline(workload, n_slices: int, slices=None):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    sl = workload.slices[:n_slices]
+    sl = (workload.slices if slices is None else slices)[:n_slices]
     q = workload.quats[:n_slices]
     oracle.insert(workload.n, sl[:8], q[:8], nthreads=threads)      # load / warm
     t0 = time.perf_counter()
@@ -89,6 +92,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--variant", default="slab", choices=["slab", "binned", "naive"])
     ap.add_argument("--batch", type=int, default=1500)
+    ap.add_argument("--dtype", default="c64", choices=["c64", "f16", "bf16"],
+                    help="slice storage: complex64, half pairs with a per-slice scale, or bfloat16 pairs")
     ap.add_argument("--cpu-slices", type=int, default=2500,
                     help="slices in the CPU-oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--plain-steps", type=int, default=1,
@@ -119,9 +124,28 @@ def main(argv=None):
     assert counts["n"] == w.n and counts["S"] == w.S
     U, U_half = int(counts["U"]), int(counts["U_half"])
 
-    slices = torch.from_numpy(w.slices).to(dev)
     quats = torch.from_numpy(w.quats).to(dev)
-    rec = recon.Reconstruction(w.n, device=dev, max_batch=args.batch)
+    scales = None
+    cpu_slices = w.slices
+    if args.dtype == "c64":
+        slices = torch.from_numpy(w.slices).to(dev)
+        slice_bytes = w.slices.nbytes + w.quats.nbytes
+        sdt = recon.RECON_SLICE_C64
+    else:
+        from synth.phantom import dequantize_slices, quantize_slices
+        bits, sc = quantize_slices(w.slices, args.dtype)
+        tdt = torch.float16 if args.dtype == "f16" else torch.bfloat16
+        slices = torch.from_numpy(bits.view(np.int16)).to(dev).view(tdt)
+        sdt = recon.RECON_SLICE_F16 if args.dtype == "f16" else recon.RECON_SLICE_BF16
+        slice_bytes = bits.nbytes + w.quats.nbytes
+        if args.dtype == "f16":
+            scales = torch.from_numpy(sc).to(dev)
+            slice_bytes += sc.nbytes
+        if args.cpu_slices > 0:        # the oracle gets the values the kernels read
+            k = min(args.cpu_slices, w.S)
+            cpu_slices = dequantize_slices(bits[:k], sc[:k], args.dtype)
+        del bits
+    rec = recon.Reconstruction(w.n, device=dev, max_batch=args.batch, slice_dtype=sdt)
     variant_ids = {"slab": recon.RECON_VARIANT_SLAB, "binned": recon.RECON_VARIANT_BINNED,
                    "naive": recon.RECON_VARIANT_NAIVE}
     rec.set_config(variant=variant_ids[args.variant])
@@ -135,7 +159,8 @@ def main(argv=None):
             s0, s1 = b * args.batch, min(w.S, (b + 1) * args.batch)
             if events is not None:
                 recon.recon_set_timing_events(rec.ctx, *events[b])
-            recon.recon_insert_batch(rec.ctx, slices[s0:s1], None, quats[s0:s1], s1 - s0)
+            recon.recon_insert_batch(rec.ctx, slices[s0:s1], None if scales is None else scales[s0:s1],
+                                     quats[s0:s1], s1 - s0)
         if events is not None:
             recon.recon_set_timing_events(rec.ctx, None, None)
         rec.finalize(out=V)
@@ -166,11 +191,12 @@ def main(argv=None):
     # roofline of the dominant kernel (the insertion kernel), per launch
     flops_per_step = FLOPS_PER_UPDATE * U_half
     achieved_tflops = flops_per_step / (kernel_ms_per_step / 1e3) / 1e12
-    slice_bytes = w.slices.nbytes + w.quats.nbytes
     half_vox = (w.n // 2 + 1) * (w.n + 1) ** 2
     gw_rmw = 2 * 12 * half_vox * nb          # G (8 B) + W (4 B) read and written per launch
     alg_bytes_step = slice_bytes + gw_rmw
-    traffic = load_traffic(nb)
+    # the stored counter run covers the default configuration only
+    traffic = load_traffic(nb) if (args.workload, args.variant, args.dtype, args.batch) == \
+        ("paper", "slab", "c64", 1500) else None
 
     plain = None
     if args.plain_steps > 0 and args.variant != "naive":
@@ -197,7 +223,7 @@ def main(argv=None):
     cpu = None
     if args.cpu_slices > 0:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, min(args.cpu_slices, w.S))
+        cpu = cpu_baseline(w, min(args.cpu_slices, w.S), cpu_slices)
 
     result = {
         "metric": "slice-sample×voxel updates/s",
@@ -214,7 +240,7 @@ def main(argv=None):
         "data": "synthetic: seeded 40-Gaussian phantom projections (exact line integrals) and their centered "
                 "DFTs, Haar-uniform orientations; stands in for EMPIAR-10010",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "n": w.n, "slices": w.S, "batch": args.batch,
-                   "variant": args.variant, "pairs_U": U, "pairs_half_box": U_half},
+                   "variant": args.variant, "slice_storage": args.dtype, "pairs_U": U, "pairs_half_box": U_half},
         "roofline": {
             "bound": "alu",
             "kernel": {"slab": "k_insert_slab", "binned": "k_insert_binned", "naive": "k_insert_naive"}[args.variant],

@@ -11,18 +11,23 @@
 //    atomics leave the wavefront.
 //  * A slice passes the tile's bin test when its plane's slab |e3.v| <= a can
 //    meet the tile.  For each passing slice the wavefront
-//      1. stages the (WIN+16)^2 rectangle of the slice that the tile's
-//         windows can touch into LDS, resolving the Hermitian half plane and
-//         the |k| < r_max disk once per sample (zero outside the disk);
-//      2. enumerates exactly the voxels inside the slab: lane = one of the
+//      1. enumerates exactly the voxels inside the slab: lane = one of the
 //         64 columns of the tile along the normal's dominant axis, whose slab
 //         run is a contiguous range; a wave prefix scan packs the runs into a
-//         hit list;
+//         hit list, and the ends of the runs bound the hits' windows (slices
+//         without hits stop here);
+//      2. stages that rectangle of the slice into LDS, resolving the
+//         Hermitian half plane and the |k| < r_max disk once per sample (zero
+//         outside the disk);
 //      3. processes the hits 64 per round, each lane evaluating the
 //         branch-free WIN x WIN window from LDS (blob table lerp from LDS)
 //         and adding its partial sums to the voxel's LDS accumulator.
+//    Steps 1 and the loads of step 2 for the next slice are issued before
+//    step 3 of the current one, so the loads overlap the window evaluation.
 //  * Two-level FP32 accumulation: LDS accumulators hold at most
 //    `inner_chunk` slices before they are folded into per-lane registers.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace recon {
@@ -42,7 +47,7 @@ struct SlabShape {
     // always suffice.
     static constexpr int RECT = WIN + 17;
     static constexpr int RECT2 = RECT * RECT;
-    static constexpr int WAVE_WORDS = ACC_WORDS + 2 * RECT2 + LIST_WORDS;
+    static constexpr int WAVE_WORDS = ACC_WORDS + 2 * RECT2 + 2 * LIST_WORDS;
 };
 
 // Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^20 T[N-1].
@@ -58,6 +63,32 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Componentwise minimum over the 64 lanes of a wavefront (all lanes active)
+// of two int16 values packed in one register: DPP permutations reduce each
+// row of 16 lanes, then the four row results are combined.
+typedef short short2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int pk_min(int a, int b)
+{
+    return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(short2_t, a),
+                                                             __builtin_bit_cast(short2_t, b)));
+}
+__device__ __forceinline__ int wave_min_pk(int v)
+{
+    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    const int r = pk_min(pk_min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+                         pk_min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    return __builtin_amdgcn_readfirstlane(r);
+}
+__device__ __forceinline__ int pack16(int lo, int hi)
+{
+    return static_cast<int>((static_cast<unsigned>(lo) & 0xffffu) | (static_cast<unsigned>(hi) << 16));
+}
+__device__ __forceinline__ int unpack16_lo(int v) { return static_cast<short>(v & 0xffff); }
+__device__ __forceinline__ int unpack16_hi(int v) { return v >> 16; }
 
 __device__ __forceinline__ float uniformf(float x)
 {
@@ -84,13 +115,14 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 template <int WIN, bool RIM, bool LERP, bool PRELOAD>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
                                            const Geom &g, float ux, float uy, float uz, float kx_lo,
-                                           float ky_lo, float &pr, float &pi, float &pw)
+                                           float ky_lo, float xspan, float yspan, float &pr, float &pi,
+                                           float &pw)
 {
     constexpr int RECT = SlabShape<WIN>::RECT;
-    const float span = static_cast<float>(RECT - WIN);
     // first window column / row as floats, kept inside the staged rectangle
-    const float fx0 = fminf(fmaxf(ceilf(ux - g.a), kx_lo), kx_lo + span);
-    const float fy0 = fminf(fmaxf(ceilf(uy - g.a), ky_lo), ky_lo + span);
+    // (the rectangle is sized to hold every window; the clamp only guards it)
+    const float fx0 = fminf(fmaxf(ceilf(ux - g.a), kx_lo), kx_lo + xspan);
+    const float fy0 = fminf(fmaxf(ceilf(uy - g.a), ky_lo), ky_lo + yspan);
     const int ox = static_cast<int>(fx0 - kx_lo);
     const int oy = static_cast<int>(fy0 - ky_lo);
     const float2 *base = rect + oy * RECT + ox;
@@ -277,169 +309,229 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
             return __builtin_amdgcn_readfirstlane(it_base + b);
         };
 
-        // Staging of one slice, split into issue (global loads into registers)
-        // and commit (LDS writes) so that the next slice's loads are in flight
-        // while the current slice's windows are evaluated.
-        struct Stage {
-            float4 e1, e2, e3;
-            int kx_lo, ky_lo;
-            int rim;          // int, not bool: no padding bytes in the struct copies
-            float scale;
-        };
-        // cell[] holds the raw sample words between issue and commit: the
-        // complex64 value, or the packed 16-bit pair in .x.  Decoding waits
-        // for the loads, so it happens at commit, after the previous slice's
-        // windows have hidden their latency.
-        float2 cell[NC];
-        bool keep[NC];
-        int dst[NC];
-        auto issue = [&](int s, Stage &st) {
-            // s is wave-uniform: the orientation and scale go to scalar
-            // registers here, so no later copy of the stage waits on the
-            // sample loads issued below
-            const Orient ov = orient[s];
-            Orient o;
-            o.e1 = uniform4(ov.e1);
-            o.e2 = uniform4(ov.e2);
-            o.e3 = uniform4(ov.e3);
-            st.e1 = o.e1;
-            st.e2 = o.e2;
-            st.e3 = o.e3;
-            const float ucx = fmaf(o.e1.x, cx, fmaf(o.e1.y, cy, o.e1.z * cz));
-            const float ucy = fmaf(o.e2.x, cx, fmaf(o.e2.y, cy, o.e2.z * cz));
-            const float extx = fmaf(hx, fabsf(o.e1.x), fmaf(hy, fabsf(o.e1.y), hz * fabsf(o.e1.z)));
-            const float exty = fmaf(hx, fabsf(o.e2.x), fmaf(hy, fabsf(o.e2.y), hz * fabsf(o.e2.z)));
-            const int kx_lo = static_cast<int>(floorf(ucx - extx - g.a)) - 1;
-            const int ky_lo = static_cast<int>(floorf(ucy - exty - g.a)) - 1;
-            const int wx = min(static_cast<int>(floorf(ucx + extx + g.a)) + 2 - kx_lo, RECT);
-            const int wy = min(static_cast<int>(floorf(ucy + exty + g.a)) + 2 - ky_lo, RECT);
-            const int fxm = max(abs(kx_lo), abs(kx_lo + wx - 1));
-            const int fym = max(abs(ky_lo), abs(ky_lo + wy - 1));
-            st.kx_lo = kx_lo;
-            st.ky_lo = ky_lo;
-            st.rim = static_cast<float>(fxm * fxm + fym * fym) < g.r2max ? 0 : 1;
-            st.scale = g.scales ? uniformf(g.scales[s]) : 1.0f;
-            const int ncell = wx * wy;
-            const float inv_wx = 1.0f / static_cast<float>(wx);
-            // buffer resource over this slice: 32-bit offsets, hardware bounds check
-            const int eb = sample_bytes(g.dtype);
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<unsigned char *>(static_cast<const unsigned char *>(slices) +
-                                            static_cast<size_t>(s) * slen * eb),
-                static_cast<short>(0), static_cast<int>(slen * eb), 0x00020000);
-            int off[NC];
-#pragma unroll
-            for (int qq = 0; qq < NC; ++qq) {
-                const int c = qq * 64 + lane;
-                const int cy_ = static_cast<int>((static_cast<float>(c) + 0.5f) * inv_wx);
-                const int cx_ = c - cy_ * wx;
-                const int kx = kx_lo + cx_, ky = ky_lo + cy_;
-                const bool valid = c < ncell && static_cast<float>(kx * kx + ky * ky) < g.r2max;
-                const bool direct = kx > 0 || (kx == 0 && ky >= 0);
-                int row = direct ? ky + g.h : g.h - ky;
-                int col = direct ? kx : -kx;
-                row = valid ? row : g.h;
-                col = valid ? col : 0;
-                off[qq] = (row * g.sw + col) * eb;
-                // the sign flip of mirrored samples is applied at commit
-                keep[qq] = valid;
-                dst[qq] = c < ncell ? (direct ? 1 : -1) * (cy_ * RECT + cx_ + 1) : 0;
-            }
-            // all loads back to back (dtype is uniform over the launch)
-            if (g.dtype == 0) {
-#pragma unroll
-                for (int qq = 0; qq < NC; ++qq)
-                    cell[qq] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off[qq], 0, 0));
-            } else {
-#pragma unroll
-                for (int qq = 0; qq < NC; ++qq)
-                    cell[qq].x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off[qq], 0, 0));
-            }
-        };
-        auto commit = [&](const Stage &st) {
-            const int dt = g.dtype;
-#pragma unroll
-            for (int qq = 0; qq < NC; ++qq) {
-                if (dst[qq] != 0) {
-                    float2 v;
-                    if (dt == 0) {
-                        v = cell[qq];
-                    } else {
-                        const unsigned raw = __float_as_uint(cell[qq].x);
-                        if (dt == 1) {
-                            const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
-                            const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
-                            v = make_float2(static_cast<float>(lo) * st.scale, static_cast<float>(hi) * st.scale);
-                        } else {
-                            v = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
-                        }
-                    }
-                    v = keep[qq] ? v : make_float2(0.f, 0.f);
-                    if (dst[qq] < 0) v.y = -v.y;
-                    rect[abs(dst[qq]) - 1] = v;
-                }
-            }
-        };
+        // The slice loop is compiled once per storage type, so no load of
+        // one type shares registers with the other's.
+        auto slice_loop = [&](auto dt_tag) {
+            constexpr int DT = decltype(dt_tag)::value;
+            // Per slice with hits: (1) enumerate the tile's voxels inside the
+            // slab into a hit list and bound their windows; (2) issue the loads
+            // of exactly that rectangle of samples; (3) commit it to LDS; (4) run
+            // the windows.  The next slice's (1) and (2) run before this slice's
+            // (4), so its loads are in flight while these windows are evaluated
+            // (two hit lists alternate).
+            struct Stage {
+                float4 e1, e2, e3;
+                int kx_lo, ky_lo, wx, wy;    // staged rectangle: columns kx_lo.., rows ky_lo..
+                int rim;                     // int, not bool: no padding bytes in the struct copies
+                int H;                       // hits
+                int nq;                      // loads per lane
+                float scale;
+            };
+            // cell[] holds the raw sample words between issue and commit: the
+            // complex64 value, or the packed 16-bit pair in .x.  Decoding waits
+            // for the loads, so it happens at commit.
+            float2 cell[NC];
+            int dst[NC];
 
-        Stage cur;
-        int s = next_slice();
-        if (s >= 0) issue(s, cur);
-        while (s >= 0) {
-            // 1. enumerate the tile's voxels inside the slab |e3.v| <= a
-            //    (and inside the reach sphere |v| < r_max + a)
-            const float4 e3 = cur.e3;
-            const float n0 = fabsf(e3.x), n1 = fabsf(e3.y), n2 = fabsf(e3.z);
-            const int d = (n0 >= n1 && n0 >= n2) ? 0 : (n1 >= n2 ? 1 : 2);
-            const int ia = d == 0 ? 1 : 0;
-            const int ib = d == 2 ? 1 : 2;
-            const float nd = sel3(d, e3.x, e3.y, e3.z);
-            const float na = sel3(ia, e3.x, e3.y, e3.z);
-            const float nb = sel3(ib, e3.x, e3.y, e3.z);
-            const int D0 = sel3i(d, X0, Y0, Z0), D1 = sel3i(d, X1, Y1, Z1);
-            const int A0 = sel3i(ia, X0, Y0, Z0), A1 = sel3i(ia, X1, Y1, Z1);
-            const int B0 = sel3i(ib, X0, Y0, Z0), B1 = sel3i(ib, X1, Y1, Z1);
-            const int sd = sel3i(d, 1, TE, TE * TE);
-            const int sa = sel3i(ia, 1, TE, TE * TE);
-            const int sb = sel3i(ib, 1, TE, TE * TE);
-            const int ca = lane & (TE - 1), cb = lane >> 3;
-            const int va = A0 + ca, vb = B0 + cb;
-            const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
-            const float rem = R2 - fmaf(fva, fva, fvb * fvb);
-            const bool col_in = va <= A1 && vb <= B1 && rem >= 0.f;
-            const float lim = sqrtf(fmaxf(rem, 0.f));
-            const float q = fmaf(na, fva, nb * fvb);
-            const float inv = 1.0f / nd;
-            const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
-            const int lo = max(static_cast<int>(ceilf(fmaxf(fminf(t1, t2), -lim))), D0);
-            const int hi = min(static_cast<int>(floorf(fminf(fmaxf(t1, t2), lim))), D1);
-            const int cnt = col_in ? max(hi - lo + 1, 0) : 0;
-            int incl = cnt;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int y = __shfl_up(incl, off);
-                if (lane >= off) incl += y;
-            }
-            const int H = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
-            if (H > 0) {
+            auto setup = [&](int s, Stage &st) {
+                // s is wave-uniform: the orientation and scale go to scalar
+                // registers, so no later copy of the stage waits on sample loads
+                const Orient ov = orient[s];
+                st.e1 = uniform4(ov.e1);
+                st.e2 = uniform4(ov.e2);
+                st.e3 = uniform4(ov.e3);
+                st.scale = g.scales ? uniformf(g.scales[s]) : 1.0f;
+            };
+
+            // (1) Voxels inside the slab |e3.v| <= a (and inside the reach sphere
+            // |v| < r_max + a): lane = one of the 64 columns of the tile along
+            // the normal's dominant axis, whose run is a contiguous range; a wave
+            // prefix scan packs the runs into the list.  The rectangle holds every
+            // window [ceil(u - a), ceil(u - a) + WIN - 1] of the hits, with 1e-3
+            // of slack for rounding (u is linear along a run, so the run's end
+            // voxels bound it).  Returns the hit count.
+            auto enumerate = [&](Stage &st, unsigned short *lst) -> int {
+                const float4 e3 = st.e3;
+                const float n0 = fabsf(e3.x), n1 = fabsf(e3.y), n2 = fabsf(e3.z);
+                // (a scalar: selections on d below stay scalar)
+                const int d = __builtin_amdgcn_readfirstlane((n0 >= n1 && n0 >= n2) ? 0 : (n1 >= n2 ? 1 : 2));
+                const int ia = d == 0 ? 1 : 0;
+                const int ib = d == 2 ? 1 : 2;
+                const float nd = sel3(d, e3.x, e3.y, e3.z);
+                const float na = sel3(ia, e3.x, e3.y, e3.z);
+                const float nb = sel3(ib, e3.x, e3.y, e3.z);
+                const int D0 = sel3i(d, X0, Y0, Z0), D1 = sel3i(d, X1, Y1, Z1);
+                const int A0 = sel3i(ia, X0, Y0, Z0), A1 = sel3i(ia, X1, Y1, Z1);
+                const int B0 = sel3i(ib, X0, Y0, Z0), B1 = sel3i(ib, X1, Y1, Z1);
+                const int sd = sel3i(d, 1, TE, TE * TE);
+                const int sa = sel3i(ia, 1, TE, TE * TE);
+                const int sb = sel3i(ib, 1, TE, TE * TE);
+                const int ca = lane & (TE - 1), cb = lane >> 3;
+                const int va = A0 + ca, vb = B0 + cb;
+                const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
+                const float rem = R2 - fmaf(fva, fva, fvb * fvb);
+                const bool col_in = va <= A1 && vb <= B1 && rem >= 0.f;
+                const float lim = sqrtf(fmaxf(rem, 0.f));
+                const float q = fmaf(na, fva, nb * fvb);
+                const float inv = 1.0f / nd;
+                const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
+                const int lo = max(static_cast<int>(ceilf(fmaxf(fminf(t1, t2), -lim))), D0);
+                const int hi = min(static_cast<int>(floorf(fminf(fmaxf(t1, t2), lim))), D1);
+                const int cnt = col_in ? max(hi - lo + 1, 0) : 0;
+                int incl = cnt;
+    #pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(incl, off);
+                    if (lane >= off) incl += y;
+                }
+                const int H = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+                st.H = H;
+                if (H == 0) return 0;
                 const int excl = incl - cnt;
                 const int lid0 = ca * sa + cb * sb + (lo - D0) * sd;
-                for (int k = 0; k < cnt; ++k) list[excl + k] = static_cast<unsigned short>(lid0 + k * sd);
-                // 2. the staged samples of this slice go to LDS
-                commit(cur);
-            }
-            // next slice's loads are issued before this slice's windows
-            Stage nxt = cur;
-            const int s_next = next_slice();
-            if (s_next >= 0) issue(s_next, nxt);
-            wave_sync();
+                // a run never exceeds the tile edge: a fixed, predicated loop
+#pragma unroll
+                for (int k = 0; k < TE; ++k)
+                    if (k < cnt) lst[excl + k] = static_cast<unsigned short>(lid0 + k * sd);
+                // in-plane coordinates of the run's end voxels, computed as the
+                // windows compute them
+                // (lanes without hits contribute the neutral 0x7fff; |coordinates|
+                // stay below n / 2 + 8 <= 520, so they fit in int16)
+                int lows = 0x7fff7fff, highs = 0x7fff7fff;
+                const float e1d = sel3(d, st.e1.x, st.e1.y, st.e1.z);
+                const float e2d = sel3(d, st.e2.x, st.e2.y, st.e2.z);
+                if (cnt > 0) {
+                    const float flo = static_cast<float>(lo);
+                    const float vx0 = d == 0 ? flo : fva;
+                    const float vy0 = d == 1 ? flo : (d == 0 ? fva : fvb);
+                    const float vz0 = d == 2 ? flo : fvb;
+                    const float ux0 = fmaf(st.e1.x, vx0, fmaf(st.e1.y, vy0, st.e1.z * vz0));
+                    const float uy0 = fmaf(st.e2.x, vx0, fmaf(st.e2.y, vy0, st.e2.z * vz0));
+                    // the other end, hi - lo steps along axis d
+                    const float run = static_cast<float>(hi - lo);
+                    const float ux1 = fmaf(run, e1d, ux0);
+                    const float uy1 = fmaf(run, e2d, uy0);
+                    const int xl = static_cast<int>(floorf(fminf(ux0, ux1) - g.a - 1e-3f));
+                    const int xh = static_cast<int>(ceilf(fmaxf(ux0, ux1) - g.a + 1e-3f)) + (WIN - 1);
+                    const int yl = static_cast<int>(floorf(fminf(uy0, uy1) - g.a - 1e-3f));
+                    const int yh = static_cast<int>(ceilf(fmaxf(uy0, uy1) - g.a + 1e-3f)) + (WIN - 1);
+                    lows = pack16(xl, yl);
+                    highs = pack16(-xh, -yh);
+                }
+                lows = wave_min_pk(lows);
+                highs = wave_min_pk(highs);
+                st.kx_lo = unpack16_lo(lows);
+                st.ky_lo = unpack16_hi(lows);
+                // never wider than WIN + 15 < RECT; min() only guards the buffer
+                st.wx = min(-unpack16_lo(highs) - st.kx_lo + 1, RECT);
+                st.wy = min(-unpack16_hi(highs) - st.ky_lo + 1, RECT);
+                const int fxm = max(abs(st.kx_lo), abs(st.kx_lo + st.wx - 1));
+                const int fym = max(abs(st.ky_lo), abs(st.ky_lo + st.wy - 1));
+                st.rim = static_cast<float>(fxm * fxm + fym * fym) < g.r2max ? 0 : 1;
+                st.nq = (st.wx * st.wy + 63) >> 6;
+                return H;
+            };
 
-            if (H > 0) {
-                // 3. windows of the hits, 64 per round
+            // (2) loads of the staged rectangle, Hermitian rule and disk applied
+            auto issue = [&](int s, const Stage &st) {
+                const int wx = st.wx;
+                const int ncell = wx * st.wy;
+                const float inv_wx = 1.0f / static_cast<float>(wx);
+                // buffer resource over this slice: 32-bit offsets, hardware bounds check
+                // (reads at or past the record size return zero: cells outside
+                // the disk are loaded from there and so stage as zero)
+                constexpr int eb = DT == 0 ? 8 : 4;
+                const int bytes = static_cast<int>(slen * eb);
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<unsigned char *>(static_cast<const unsigned char *>(slices) +
+                                                static_cast<size_t>(s) * slen * eb),
+                    static_cast<short>(0), bytes, 0x00020000);
+                int off[NC];
+    #pragma unroll
+                for (int qq = 0; qq < NC; ++qq) {
+                    if (qq >= st.nq) break;
+                    const int c = qq * 64 + lane;
+                    const int cy_ = static_cast<int>((static_cast<float>(c) + 0.5f) * inv_wx);
+                    const int cx_ = c - cy_ * wx;
+                    const int kx = st.kx_lo + cx_, ky = st.ky_lo + cy_;
+                    const bool valid = c < ncell && static_cast<float>(kx * kx + ky * ky) < g.r2max;
+                    const bool direct = kx > 0 || (kx == 0 && ky >= 0);
+                    const int row = direct ? ky + g.h : g.h - ky;
+                    const int col = direct ? kx : -kx;
+                    off[qq] = valid ? (row * g.sw + col) * eb : bytes;
+                    // the sign flip of mirrored samples is applied at commit
+                    dst[qq] = c < ncell ? (direct ? 1 : -1) * (cy_ * RECT + cx_ + 1) : 0;
+                }
+                // all loads back to back; only as many as the rectangle needs
+                // (st.nq is wave-uniform)
+                if constexpr (DT == 0) {
+    #pragma unroll
+                    for (int qq = 0; qq < NC; ++qq)
+                        if (qq < st.nq)
+                            cell[qq] = __builtin_bit_cast(float2,
+                                                          __builtin_amdgcn_raw_buffer_load_b64(rs, off[qq], 0, 0));
+                } else {
+    #pragma unroll
+                    for (int qq = 0; qq < NC; ++qq)
+                        if (qq < st.nq)
+                            cell[qq].x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off[qq], 0, 0));
+                }
+            };
+
+            // (3) decode and write the staged samples to LDS
+            auto commit = [&](const Stage &st) {
+    #pragma unroll
+                for (int qq = 0; qq < NC; ++qq) {
+                    if (qq < st.nq && dst[qq] != 0) {
+                        float2 v;
+                        if constexpr (DT == 0) {
+                            v = cell[qq];
+                        } else {
+                            const unsigned raw = __float_as_uint(cell[qq].x);
+                            if constexpr (DT == 1) {
+                                const _Float16 lo = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw & 0xffffu));
+                                const _Float16 hi = __builtin_bit_cast(_Float16, static_cast<unsigned short>(raw >> 16));
+                                v = make_float2(static_cast<float>(lo) * st.scale, static_cast<float>(hi) * st.scale);
+                            } else {
+                                v = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
+                            }
+                        }
+                        if (dst[qq] < 0) v.y = -v.y;
+                        rect[abs(dst[qq]) - 1] = v;
+                    }
+                }
+            };
+
+            // next slice of the item that has hits: enumerated into lst, loads issued
+            auto advance = [&](Stage &st, unsigned short *lst) -> int {
+                for (;;) {
+                    const int s = next_slice();
+                    if (s < 0) return -1;
+                    setup(s, st);
+                    if (enumerate(st, lst) > 0) {
+                        issue(s, st);
+                        return s;
+                    }
+                }
+            };
+
+            Stage cur, nxt;
+            unsigned short *list_cur = list, *list_nxt = list + TV;
+            int s = advance(cur, list_cur);
+            while (s >= 0) {
+                commit(cur);
+                const int s_next = advance(nxt, list_nxt);
+                wave_sync();
+
+                // (4) windows of the hits, 64 per round
+                const float4 e3 = cur.e3;
+                const int H = cur.H;
                 const float fkx_lo = static_cast<float>(cur.kx_lo), fky_lo = static_cast<float>(cur.ky_lo);
+                const float xspan = static_cast<float>(cur.wx - WIN), yspan = static_cast<float>(cur.wy - WIN);
                 for (int r = 0; r < H; r += 64) {
                     const int hh = r + lane;
                     if (hh < H) {
-                        const int lid = list[hh];
+                        const int lid = list_cur[hh];
                         const float vx = static_cast<float>(X0 + (lid & 7));
                         const float vy = static_cast<float>(Y0 + ((lid >> 3) & 7));
                         const float vz = static_cast<float>(Z0 + (lid >> 6));
@@ -449,9 +541,11 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                         float pr, pi, pw;
                         constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
                         if (cur.rim)
-                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, pr, pi, pw);
+                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, xspan, yspan,
+                                                             pr, pi, pw);
                         else
-                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, pr, pi, pw);
+                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, xspan, yspan,
+                                                              pr, pi, pw);
                         // a voxel appears once per slice: single writer within the wave
                         if (FLAGS & SLAB_ATOMIC) {
                             atomicAdd(acc_re + lid, pr);
@@ -466,7 +560,7 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 }
                 wave_sync();
                 if (++inner == inner_chunk) {
-#pragma unroll
+    #pragma unroll
                     for (int k = 0; k < TV / 64; ++k) {
                         const int lid = lane + 64 * k;
                         ore[k] += acc_re[lid];
@@ -479,10 +573,19 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                     inner = 0;
                     wave_sync();
                 }
+                cur = nxt;
+                unsigned short *t = list_cur;
+                list_cur = list_nxt;
+                list_nxt = t;
+                s = s_next;
             }
-            cur = nxt;
-            s = s_next;
-        }
+        };
+        if (g.dtype == 0)
+            slice_loop(std::integral_constant<int, 0>{});
+        else if (g.dtype == 1)
+            slice_loop(std::integral_constant<int, 1>{});
+        else
+            slice_loop(std::integral_constant<int, 2>{});
 #pragma unroll
         for (int k = 0; k < TV / 64; ++k) {
             const int lid = lane + 64 * k;
@@ -581,7 +684,7 @@ size_t slab_lds_bytes(const Geom &g, int waves_per_block)
 {
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
     const int rect = win + 17;
-    const size_t wave_words = ACC_WORDS + 2 * rect * rect + LIST_WORDS;
+    const size_t wave_words = ACC_WORDS + 2 * rect * rect + 2 * LIST_WORDS;
     return (static_cast<size_t>(table_words(g.N)) + waves_per_block * wave_words) * sizeof(float);
 }
 

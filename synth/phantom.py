@@ -19,7 +19,12 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+import os
+
 import numpy as np
+import scipy.fft
+
+_FFT_WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 # --------------------------------------------------------------------------
@@ -143,8 +148,10 @@ def project(ph: Phantom, quats: np.ndarray, n: int) -> np.ndarray:
 
 
 def slices_from_projections(P: np.ndarray) -> np.ndarray:
-    """Centered DFT of each projection in half-plane layout [S][n][n/2+1] (complex128)."""
-    F = np.fft.rfft2(np.fft.ifftshift(P, axes=(-2, -1)), axes=(-2, -1))
+    """Centered DFT of each projection in half-plane layout [S][n][n/2+1] (complex128).
+
+    SciPy's FFT is the same pocketfft code as NumPy's, run on several threads."""
+    F = scipy.fft.rfft2(np.fft.ifftshift(P, axes=(-2, -1)), axes=(-2, -1), workers=_FFT_WORKERS)
     return np.fft.fftshift(F, axes=-2)
 
 

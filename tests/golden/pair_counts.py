@@ -6,7 +6,8 @@ the full box; U_half counts those whose voxel has x >= 0 (the half box the
 GPU kernels accumulate).  The benchmark divides these counts by its measured
 times to report updates per second.
 
-Run:  python tests/golden/pair_counts.py
+Run:  python tests/golden/pair_counts.py [name ...]   (default: small paper precision)
+Entries for names not given are kept.
 """
 import json
 import os
@@ -21,8 +22,11 @@ import synth  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "pair_counts.json")
 
 
-def main(names=("small", "paper")):
+def main(names=("small", "paper", "precision")):
     data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
     for name in names:
         w = synth.make_workload(name)
         _, _, U, Uh = oracle.insert(w.n, w.slices, w.quats, with_half=True,
@@ -35,4 +39,4 @@ def main(names=("small", "paper")):
 
 
 if __name__ == "__main__":
-    main()
+    main(tuple(sys.argv[1:]) or ("small", "paper", "precision"))
