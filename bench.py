@@ -148,7 +148,7 @@ def main(argv=None):
     rec = recon.Reconstruction(w.n, device=dev, max_batch=args.batch, slice_dtype=sdt)
     variant_ids = {"slab": recon.RECON_VARIANT_SLAB, "binned": recon.RECON_VARIANT_BINNED,
                    "naive": recon.RECON_VARIANT_NAIVE}
-    rec.set_config(variant=variant_ids[args.variant])
+    rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0)
     V = torch.empty_like(rec.G)
     nb = (w.S + args.batch - 1) // args.batch
     stream = torch.cuda.current_stream()
@@ -200,7 +200,7 @@ def main(argv=None):
 
     plain = None
     if args.plain_steps > 0 and args.variant != "naive":
-        rec.set_config(variant=recon.RECON_VARIANT_NAIVE)
+        rec.set_config(variant=recon.RECON_VARIANT_NAIVE, waves_per_block=0, slab_flags=0)
         step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -209,7 +209,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         plain_ms = 1e3 * (time.perf_counter() - t1) / args.plain_steps
         plain = {"value": U / (plain_ms / 1e3), "ms_per_step": plain_ms, "variant": "naive"}
-        rec.set_config(variant=variant_ids[args.variant])
+        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0)
 
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20

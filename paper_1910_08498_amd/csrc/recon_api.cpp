@@ -212,6 +212,14 @@ recon_config default_config()
 
 int default_waves(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 16; }
 
+// The slab kernel's 11-wave instance exists for the 4 x 4 window (blob
+// radius in [1.5, 2)) with table interpolation, and needs its LDS to fit.
+bool slab_wide_ok(const recon::Geom &g, bool lerp, size_t max_lds)
+{
+    const int win = static_cast<int>(std::floor(2.0f * g.a)) + 1;
+    return win == 4 && lerp && recon::slab_lds_bytes(g, 11) <= max_lds;
+}
+
 // State of a dynamic-tuning search (random search over the tuning space).
 struct TuneState {
     bool active = false;
@@ -524,7 +532,9 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     recon_config d = default_config();
     recon_config n = cfg ? *cfg : d;
     if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
+    const bool wide = n.variant == RECON_VARIANT_SLAB && slab_wide_ok(c->g, c->p.table_lerp != 0, c->max_lds);
     if (n.waves_per_block == 0) n.waves_per_block = default_waves(n.variant);
+    if (n.slab_flags == 0 && n.waves_per_block == 11) n.slab_flags = 4;
     if (n.group == 0) n.group = d.group;
     if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
     if (n.split == 0) n.split = d.split;
@@ -533,8 +543,10 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED && n.variant != RECON_VARIANT_SLAB)
         return fail(RECON_ECONFIG, "unknown variant %d", n.variant);
     const int wpb = n.waves_per_block;
-    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 12 && wpb != 16)
-        return fail(RECON_ECONFIG, "waves_per_block must be 1, 2, 4, 8, 12 or 16");
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 11 && wpb != 12 && wpb != 16)
+        return fail(RECON_ECONFIG, "waves_per_block must be 1, 2, 4, 8, 11, 12 or 16");
+    if (wpb == 11 && n.variant != RECON_VARIANT_SLAB)
+        return fail(RECON_ECONFIG, "11 waves per work-group is a slab-kernel configuration");
     if (64 * wpb > c->max_threads) return fail(RECON_ECONFIG, "work-group of %d threads exceeds device", 64 * wpb);
     if (n.group < 1 || n.group > 16) return fail(RECON_ECONFIG, "group must be in [1, 16]");
     if (n.inner_chunk < 1 || n.inner_chunk > 256) return fail(RECON_ECONFIG, "inner_chunk must be in [1, 256]");
@@ -542,8 +554,9 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     if (n.variant == RECON_VARIANT_BINNED &&
         static_cast<size_t>(c->p.table_size) * sizeof(float2) > c->max_lds)
         return fail(RECON_ECONFIG, "blob table of %d entries does not fit in LDS", c->p.table_size);
-    if (n.variant == RECON_VARIANT_SLAB && wpb > 8)
-        return fail(RECON_ECONFIG, "slab kernel runs at most 8 waves per work-group");
+    if (n.variant == RECON_VARIANT_SLAB && wpb > 8 && !(wpb == 11 && wide))
+        return fail(RECON_ECONFIG, "slab kernel runs at most 8 waves per work-group, or 11 for the 4x4 window "
+                                   "with table interpolation");
     if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, wpb) > c->max_lds)
         return fail(RECON_ECONFIG, "slab kernel needs %zu bytes of LDS with %d waves (device: %zu)",
                     recon::slab_lds_bytes(c->g, wpb), wpb, c->max_lds);
@@ -570,15 +583,16 @@ static std::vector<recon_config> tuning_space(const recon_ctx *c)
     std::vector<recon_config> out;
     const int variants[3] = {RECON_VARIANT_SLAB, RECON_VARIANT_BINNED, RECON_VARIANT_NAIVE};
     for (int v : variants) {
-        std::vector<int> waves = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 8}
+        std::vector<int> waves = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 8, 11}
                                  : v == RECON_VARIANT_BINNED ? std::vector<int>{8, 16}
                                                              : std::vector<int>{4, 8, 16};
         std::vector<int> splits = v == RECON_VARIANT_NAIVE ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
-        std::vector<int> flags = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{6};
         for (int wpb : waves)
             for (int inner : {16, 32, 64})
                 for (int sp : splits)
-                    for (int fl : flags) {
+                    for (int fl : (v != RECON_VARIANT_SLAB ? std::vector<int>{6}
+                                   : wpb == 11 ? std::vector<int>{4, 5}      // no window preload at 11 waves
+                                               : std::vector<int>{4, 5, 6, 7})) {
                         recon_config in;
                         std::memset(&in, 0, sizeof(in));
                         in.variant = v;

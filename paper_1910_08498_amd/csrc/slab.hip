@@ -39,15 +39,22 @@ constexpr int TV = TE * TE * TE;       // voxels per tile
 constexpr int ACC_WORDS = 3 * TV;      // re[512], im[512], w[512]
 constexpr int LIST_WORDS = TV / 2;     // 512 uint16 voxel ids
 
+// The staged rectangle spans columns floor(u_min - a - 1e-3) to
+// ceil(u_max - a + 1e-3) + WIN - 1 over the hits' in-plane coordinate u, so
+// its width is below u_max - u_min + WIN + 2.002; the hits are voxels of one
+// tile, so u_max - u_min <= 7 (|e_x| + |e_y| + |e_z|) <= 7 sqrt(3) < 12.13,
+// and WIN + 14 cells always suffice.
+__host__ __device__ constexpr int slab_rect(int win) { return win + 14; }
+__host__ __device__ constexpr int slab_wave_words(int win)
+{
+    return ACC_WORDS + 2 * slab_rect(win) * slab_rect(win) + 2 * LIST_WORDS;
+}
+
 template <int WIN>
 struct SlabShape {
-    // The rectangle must hold every window of the tile: its width is at most
-    // 2 * ext + 2a + 4 with ext <= 3.5 * sqrt(3) (half the tile diagonal
-    // projected on a slice axis) and WIN = floor(2a) + 1, so WIN + 17 cells
-    // always suffice.
-    static constexpr int RECT = WIN + 17;
+    static constexpr int RECT = slab_rect(WIN);
     static constexpr int RECT2 = RECT * RECT;
-    static constexpr int WAVE_WORDS = ACC_WORDS + 2 * RECT2 + 2 * LIST_WORDS;
+    static constexpr int WAVE_WORDS = slab_wave_words(WIN);
 };
 
 // Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^20 T[N-1].
@@ -109,32 +116,34 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 }
 
 // Window of one (voxel, slice) hit from the LDS rectangle (row stride RECT)
-// whose cell (0, 0) is sample (kx_lo, ky_lo).  All LDS reads of the window
-// are issued before any is consumed.  RIM: the rectangle reaches the disk
-// edge, so each candidate's |k| < r_max membership gates its weight.
+// whose cell (0, 0) is sample (kx_lo, ky_lo).  The hit's coordinates arrive
+// scaled by s = sqrt(table scale), so squared distances are table positions
+// directly.  RIM: the rectangle reaches the disk edge, so each candidate's
+// |k| < r_max membership gates its weight.  PRELOAD: all LDS reads of the
+// window are issued before any is consumed.
 template <int WIN, bool RIM, bool LERP, bool PRELOAD>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
-                                           const Geom &g, float ux, float uy, float uz, float kx_lo,
-                                           float ky_lo, float xspan, float yspan, float &pr, float &pi,
-                                           float &pw)
+                                           const Geom &g, float uxs, float uys, float uzs, float s, float inv_s,
+                                           int kx_lo, int ky_lo, float &pr, float &pi, float &pw)
 {
     constexpr int RECT = SlabShape<WIN>::RECT;
-    // first window column / row as floats, kept inside the staged rectangle
-    // (the rectangle is sized to hold every window; the clamp only guards it)
-    const float fx0 = fminf(fmaxf(ceilf(ux - g.a), kx_lo), kx_lo + xspan);
-    const float fy0 = fminf(fmaxf(ceilf(uy - g.a), ky_lo), ky_lo + yspan);
-    const int ox = static_cast<int>(fx0 - kx_lo);
-    const int oy = static_cast<int>(fy0 - ky_lo);
-    const float2 *base = rect + oy * RECT + ox;
-    const float ts = g.tscale;
+    // largest first-cell offset that keeps the window inside the buffer
+    constexpr int MAXOFF = RECT * RECT - 1 - (WIN - 1) * (RECT + 1);
+    // first window column / row: ceil(u - a)
+    const float fx0 = ceilf(fmaf(uxs, inv_s, -g.a));
+    const float fy0 = ceilf(fmaf(uys, inv_s, -g.a));
+    // the staged rectangle holds every window; the clamp only guards the buffer
+    const int off = min(max((static_cast<int>(fy0) - ky_lo) * RECT + (static_cast<int>(fx0) - kx_lo), 0), MAXOFF);
+    const float2 *base = rect + off;
     float dxs[WIN], dys[WIN];
-    const float uzs = uz * uz;
+    const float dx0 = fmaf(-s, fx0, uxs), dy0 = fmaf(-s, fy0, uys);
+    const float uz2 = uzs * uzs;
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {
-        const float dx = ux - (fx0 + static_cast<float>(i));
-        dxs[i] = dx * dx * ts;
-        const float dy = uy - (fy0 + static_cast<float>(i));
-        dys[i] = fmaf(dy, dy, uzs) * ts;
+        const float dx = fmaf(-s, static_cast<float>(i), dx0);
+        dxs[i] = dx * dx;
+        const float dy = fmaf(-s, static_cast<float>(i), dy0);
+        dys[i] = fmaf(dy, dy, uz2);
     }
     float sr = 0.f, si = 0.f, sw = 0.f;
     auto weight = [&](float tk, float t0k, float t1k, int i, int j) {
@@ -209,8 +218,11 @@ constexpr int SLAB_PRELOAD = 2;   // issue all window reads before use
 template <int WIN>
 constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 
-template <int WIN, bool LERP, int FLAGS>
-__global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
+// MAXW: largest work-group (in waves) the instance is built for; it sets the
+// register budget (8 waves: 256 VGPRs, two waves per SIMD; 11 waves: 168
+// VGPRs, three waves on three of the four SIMDs).
+template <int WIN, bool LERP, int FLAGS, int MAXW>
+__global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
                                                      const Item *__restrict__ items, int nitems, int inner_chunk,
                                                      Counters *__restrict__ ctr)
 {
@@ -232,12 +244,16 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // per-wave region: the staged rectangle first (its base has no constant
+    // part, so the window's cell offsets fit the LDS instructions' offset
+    // fields), then the accumulators (re, im pairs and weights), then two
+    // hit lists
     float *wregion = smem + table_words(N) + wave * SS::WAVE_WORDS;
-    float *acc_re = wregion;
-    float *acc_im = wregion + TV;
-    float *acc_w = wregion + 2 * TV;
-    float2 *rect = reinterpret_cast<float2 *>(wregion + ACC_WORDS);
-    unsigned short *list = reinterpret_cast<unsigned short *>(wregion + ACC_WORDS + 2 * RECT2);
+    float2 *rect = reinterpret_cast<float2 *>(wregion);
+    float *accs = wregion + 2 * RECT2;
+    float2 *acc_c = reinterpret_cast<float2 *>(accs);
+    float *acc_w = accs + 2 * TV;
+    unsigned short *list = reinterpret_cast<unsigned short *>(wregion + 2 * RECT2 + ACC_WORDS);
 
     for (;;) {
         unsigned it = 0;
@@ -262,6 +278,9 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
         // voxels with |v| >= r_max + a receive nothing (every sample has |p| < r_max)
         const float R2 = (rmax + g.a + 1e-3f) * (rmax + g.a + 1e-3f);
         const float a_run = g.a * (1.0f + 1e-5f) + 1e-5f;
+        // square root of the table scale (N - 1) / a^2 and its inverse
+        const float ts_root = sqrtf(g.tscale);
+        const float ts_rinv = 1.0f / ts_root;
         const int tx = tile % TX;
         const int ty = (tile / TX) % TY;
         const int tz = tile / (TX * TY);
@@ -275,7 +294,7 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
         const int s0 = static_cast<int>(static_cast<long>(count) * item.part / item.nparts);
         const int s1 = static_cast<int>(static_cast<long>(count) * (item.part + 1) / item.nparts);
 
-        for (int k = lane; k < ACC_WORDS; k += 64) wregion[k] = 0.f;
+        for (int k = lane; k < ACC_WORDS; k += 64) accs[k] = 0.f;
         float ore[TV / 64], oim[TV / 64], ow[TV / 64];
 #pragma unroll
         for (int k = 0; k < TV / 64; ++k) ore[k] = oim[k] = ow[k] = 0.f;
@@ -422,7 +441,7 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 highs = wave_min_pk(highs);
                 st.kx_lo = unpack16_lo(lows);
                 st.ky_lo = unpack16_hi(lows);
-                // never wider than WIN + 15 < RECT; min() only guards the buffer
+                // never wider than RECT; min() only guards the buffer
                 st.wx = min(-unpack16_lo(highs) - st.kx_lo + 1, RECT);
                 st.wy = min(-unpack16_hi(highs) - st.ky_lo + 1, RECT);
                 const int fxm = max(abs(st.kx_lo), abs(st.kx_lo + st.wx - 1));
@@ -524,10 +543,11 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                 wave_sync();
 
                 // (4) windows of the hits, 64 per round
-                const float4 e3 = cur.e3;
                 const int H = cur.H;
-                const float fkx_lo = static_cast<float>(cur.kx_lo), fky_lo = static_cast<float>(cur.ky_lo);
-                const float xspan = static_cast<float>(cur.wx - WIN), yspan = static_cast<float>(cur.wy - WIN);
+                // orientation scaled by s: coordinates in table units
+                const float4 e1s = make_float4(cur.e1.x * ts_root, cur.e1.y * ts_root, cur.e1.z * ts_root, 0.f);
+                const float4 e2s = make_float4(cur.e2.x * ts_root, cur.e2.y * ts_root, cur.e2.z * ts_root, 0.f);
+                const float4 e3s = make_float4(cur.e3.x * ts_root, cur.e3.y * ts_root, cur.e3.z * ts_root, 0.f);
                 for (int r = 0; r < H; r += 64) {
                     const int hh = r + lane;
                     if (hh < H) {
@@ -535,25 +555,27 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
                         const float vx = static_cast<float>(X0 + (lid & 7));
                         const float vy = static_cast<float>(Y0 + ((lid >> 3) & 7));
                         const float vz = static_cast<float>(Z0 + (lid >> 6));
-                        const float ux = fmaf(cur.e1.x, vx, fmaf(cur.e1.y, vy, cur.e1.z * vz));
-                        const float uy = fmaf(cur.e2.x, vx, fmaf(cur.e2.y, vy, cur.e2.z * vz));
-                        const float uz = fmaf(e3.x, vx, fmaf(e3.y, vy, e3.z * vz));
+                        const float uxs = fmaf(e1s.x, vx, fmaf(e1s.y, vy, e1s.z * vz));
+                        const float uys = fmaf(e2s.x, vx, fmaf(e2s.y, vy, e2s.z * vz));
+                        const float uzs = fmaf(e3s.x, vx, fmaf(e3s.y, vy, e3s.z * vz));
                         float pr, pi, pw;
                         constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
                         if (cur.rim)
-                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, xspan, yspan,
-                                                             pr, pi, pw);
+                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, uxs, uys, uzs, ts_root, ts_rinv,
+                                                             cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         else
-                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, ux, uy, uz, fkx_lo, fky_lo, xspan, yspan,
-                                                              pr, pi, pw);
+                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, uxs, uys, uzs, ts_root, ts_rinv,
+                                                              cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         // a voxel appears once per slice: single writer within the wave
                         if (FLAGS & SLAB_ATOMIC) {
-                            atomicAdd(acc_re + lid, pr);
-                            atomicAdd(acc_im + lid, pi);
+                            atomicAdd(&acc_c[lid].x, pr);
+                            atomicAdd(&acc_c[lid].y, pi);
                             atomicAdd(acc_w + lid, pw);
                         } else {
-                            acc_re[lid] += pr;
-                            acc_im[lid] += pi;
+                            float2 c = acc_c[lid];
+                            c.x += pr;
+                            c.y += pi;
+                            acc_c[lid] = c;
                             acc_w[lid] += pw;
                         }
                     }
@@ -563,11 +585,11 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
     #pragma unroll
                     for (int k = 0; k < TV / 64; ++k) {
                         const int lid = lane + 64 * k;
-                        ore[k] += acc_re[lid];
-                        oim[k] += acc_im[lid];
+                        const float2 c = acc_c[lid];
+                        ore[k] += c.x;
+                        oim[k] += c.y;
                         ow[k] += acc_w[lid];
-                        acc_re[lid] = 0.f;
-                        acc_im[lid] = 0.f;
+                        acc_c[lid] = make_float2(0.f, 0.f);
                         acc_w[lid] = 0.f;
                     }
                     inner = 0;
@@ -589,8 +611,9 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
 #pragma unroll
         for (int k = 0; k < TV / 64; ++k) {
             const int lid = lane + 64 * k;
-            ore[k] += acc_re[lid];
-            oim[k] += acc_im[lid];
+            const float2 c = acc_c[lid];
+            ore[k] += c.x;
+            oim[k] += c.y;
             ow[k] += acc_w[lid];
         }
         wave_sync();
@@ -631,14 +654,15 @@ __global__ __launch_bounds__(512) void k_insert_slab(JobTable jt, const float2 *
     }
 }
 
-template <int WIN, bool LERP, int FLAGS>
+template <int WIN, bool LERP, int FLAGS, int MAXW = 8>
 hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *items, int nitems, int inner_chunk,
                          int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
     const size_t lds = (static_cast<size_t>(table_words(jt.job[0].g.N)) +
                         static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
-    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table, items,
-                       nitems, inner_chunk, ctr);
+    if (wpb > MAXW) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS, MAXW>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
+                       items, nitems, inner_chunk, ctr);
     return hipGetLastError();
 }
 
@@ -683,9 +707,8 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
 size_t slab_lds_bytes(const Geom &g, int waves_per_block)
 {
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
-    const int rect = win + 17;
-    const size_t wave_words = ACC_WORDS + 2 * rect * rect + 2 * LIST_WORDS;
-    return (static_cast<size_t>(table_words(g.N)) + waves_per_block * wave_words) * sizeof(float);
+    return (static_cast<size_t>(table_words(g.N)) +
+            static_cast<size_t>(waves_per_block) * slab_wave_words(win)) * sizeof(float);
 }
 
 hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
@@ -696,6 +719,13 @@ hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const fl
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
     // every flag combination exists for the common window (a in [1.5, 2)) with
     // linear interpolation; other windows and truncation use the default flags
+    if (win == 4 && lerp && wpb > 8) {
+        // three waves per SIMD: register budget of 168, window reads interleaved
+        if (flags & SLAB_ATOMIC)
+            return launch_slab_t<4, true, SLAB_ATOMIC, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr,
+                                                           st);
+        return launch_slab_t<4, true, 0, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+    }
     if (win == 4 && lerp) {
         switch (flags & 3) {
         case 0: return launch_slab_t<4, true, 0>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);

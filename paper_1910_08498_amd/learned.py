@@ -10,6 +10,12 @@ against the fastest measured one (exhaustive search).
 
 Features of a workload: log2(n), log2(slices), blob radius a.  (The device is
 fixed, so its compute-unit count is not a feature here.)
+
+Configurations are identified by their knob values (variant, waves per
+work-group, inner chunk, split, slab flags).  The runnable set depends on the
+workload (some kernel instances exist only for some blob windows), so the
+predictor scores the union of the configurations seen in training and only
+runnable ones are chosen for a workload.
 """
 from __future__ import annotations
 
@@ -24,16 +30,44 @@ from . import recon
 N_HIDDEN = 64
 
 
+def config_key(c) -> tuple:
+    return (int(c.variant), int(c.waves_per_block), int(c.inner_chunk), int(c.split), int(c.slab_flags))
+
+
 @dataclass
 class TuneRecord:
     n: int
     slices: int
     a: float
     ns_per_slice: np.ndarray            # [C] insertion-kernel time per slice of each configuration
+    keys: list = field(default_factory=list)     # [C] configuration keys, aligned with ns_per_slice
+    default_key: tuple | None = None    # the library's default configuration for this workload
     meta: dict = field(default_factory=dict)
 
     def features(self) -> np.ndarray:
         return np.array([math.log2(self.n), math.log2(self.slices), self.a], dtype=np.float64)
+
+
+def union_keys(records) -> list:
+    """Configuration keys of all records, in first-seen order."""
+    seen, out = set(), []
+    for r in records:
+        for k in r.keys:
+            if k not in seen:
+                seen.add(k)
+                out.append(k)
+    return out
+
+
+def time_matrix(records, keys) -> np.ndarray:
+    """[W, C] time per slice; +inf where a configuration does not run on a workload."""
+    col = {k: i for i, k in enumerate(keys)}
+    ns = np.full((len(records), len(keys)), np.inf)
+    for w, r in enumerate(records):
+        for k, t in zip(r.keys, r.ns_per_slice):
+            if k in col:
+                ns[w, col[k]] = t
+    return ns
 
 
 def sample_workloads(seed: int, count: int, n_range=(48, 384), s_range=(1000, 50000), a_range=(1.5, 2.5)):
@@ -62,14 +96,18 @@ def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, 
     sl = torch.view_as_complex(sl).contiguous()
     q = torch.randn((count, 4), generator=g, device=dev, dtype=torch.float32)
     rec = recon.Reconstruction(n, device=dev, max_batch=count, blob_radius=float(np.float32(a)))
+    default_key = config_key(recon.recon_get_config(rec.ctx))
     size = recon.recon_tune_space_size(rec.ctx)
     ns = np.zeros(size)
+    keys = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()       # torch creates the events on first record; the library re-records them
     e1.record()
     torch.cuda.synchronize()
     for i in range(size):
-        recon.recon_set_config(rec.ctx, recon.recon_tune_space_config(rec.ctx, i))
+        cfg = recon.recon_tune_space_config(rec.ctx, i)
+        keys.append(config_key(cfg))
+        recon.recon_set_config(rec.ctx, cfg)
         best = float("inf")
         for _ in range(repeats + 1):          # first run warms the configuration
             recon.recon_set_timing_events(rec.ctx, e0, e1)
@@ -79,11 +117,12 @@ def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, 
             best = min(best, e0.elapsed_time(e1))
         ns[i] = best * 1e6 / count
     rec.close()
-    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns)
+    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns, keys=keys, default_key=default_key)
 
 
 def soft_targets(ns: np.ndarray, temperature: float = 0.02) -> np.ndarray:
-    """Target distribution over configurations: softmax of -(t / t_best) / T."""
+    """Target distribution over configurations: softmax of -(t / t_best) / T
+    (configurations that do not run, t = +inf, get zero mass)."""
     r = -(ns / ns.min(axis=1, keepdims=True)) / temperature
     r -= r.max(axis=1, keepdims=True)
     e = np.exp(r)
@@ -145,28 +184,32 @@ def regret(ns: np.ndarray, choice: np.ndarray) -> np.ndarray:
 
 
 def random_search_regret(ns: np.ndarray, steps: int, trials: int = 200, seed: int = 0) -> np.ndarray:
-    """Expected regret of the best of `steps` random configurations (the
-    paper's random search with a fixed budget), averaged over trials."""
+    """Expected regret of the best of `steps` random runnable configurations
+    (the paper's random search with a fixed budget), averaged over trials."""
     rng = np.random.default_rng(seed)
-    W, C = ns.shape
+    W, _ = ns.shape
     out = np.zeros(W)
-    for _ in range(trials):
-        picks = np.array([rng.choice(C, size=min(steps, C), replace=False) for _ in range(W)])
-        best = ns[np.arange(W)[:, None], picks].min(axis=1)
-        out += best / ns.min(axis=1) - 1.0
+    for w in range(W):
+        ok = np.flatnonzero(np.isfinite(ns[w]))
+        for _ in range(trials):
+            picks = rng.choice(ok, size=min(steps, ok.size), replace=False)
+            out[w] += ns[w, picks].min() / ns[w, ok].min() - 1.0
     return out / trials
 
 
 def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temperature: float = 0.02,
-             seed: int = 0, default_index: int | None = None, search_budget: int = 10) -> dict:
+             seed: int = 0, search_budget: int = 10) -> dict:
     """Trains on `train` records and reports regrets on `test` records."""
+    keys = union_keys(train)
     Xtr = np.stack([r.features() for r in train])
-    Ytr = soft_targets(np.stack([r.ns_per_slice for r in train]), temperature)
+    Ytr = soft_targets(time_matrix(train, keys), temperature)
     Xte = np.stack([r.features() for r in test])
-    NSte = np.stack([r.ns_per_slice for r in test])
+    NSte = time_matrix(test, keys)
     model = Predictor(Ytr.shape[1], seed=seed)
     losses = model.fit(Xtr, Ytr, steps=steps, lr=lr)
-    pred = model.predict(Xte).argmax(axis=1)
+    scores = np.where(np.isfinite(NSte), model.predict(Xte), -np.inf)    # only runnable choices
+    pred = scores.argmax(axis=1)
+    fin = np.where(np.isfinite(NSte), NSte, np.nan)
     out = {
         "train_workloads": len(train), "test_workloads": len(test), "configs": int(Ytr.shape[1]),
         "loss_first": losses[0], "loss_last": losses[-1],
@@ -174,10 +217,11 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
         "regret_learned_max": float(regret(NSte, pred).max()),
         "regret_random_search_mean": float(random_search_regret(NSte, search_budget, seed=seed).mean()),
         "random_search_budget": search_budget,
-        "mean_config_over_best": float((NSte.mean(axis=1) / NSte.min(axis=1)).mean()),
+        "mean_config_over_best": float((np.nanmean(fin, axis=1) / NSte.min(axis=1)).mean()),
     }
-    if default_index is not None:
-        d = np.full(len(test), default_index)
+    col = {k: i for i, k in enumerate(keys)}
+    if all(r.default_key in col and np.isfinite(NSte[w, col[r.default_key]]) for w, r in enumerate(test)):
+        d = np.array([col[r.default_key] for r in test])
         out["regret_default_mean"] = float(regret(NSte, d).mean())
     return out
 
@@ -195,15 +239,6 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    rec0 = recon.Reconstruction(64, device="cuda:0")
-    cur = recon.recon_get_config(rec0.ctx)
-    default_index = None
-    for i in range(recon.recon_tune_space_size(rec0.ctx)):
-        c = recon.recon_tune_space_config(rec0.ctx, i)
-        if (c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags) == \
-                (cur.variant, cur.waves_per_block, cur.inner_chunk, cur.split, cur.slab_flags):
-            default_index = i
-    rec0.close()
     t0 = time.time()
     records = []
     params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
@@ -213,13 +248,14 @@ def main(argv=None):
         print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} "
               f"best {records[-1].ns_per_slice.min():.1f} ns/slice ({time.time() - t0:.0f} s)",
               file=sys.stderr, flush=True)
-    res = evaluate(records[:args.train], records[args.train:], steps=args.steps, default_index=default_index)
+    res = evaluate(records[:args.train], records[args.train:], steps=args.steps)
     res["collection_s"] = time.time() - t0
     res["batch_cap"] = args.batch_cap
     print(json.dumps(res), flush=True)
     if args.out:
+        keys = union_keys(records)
         np.savez(args.out, features=np.stack([r.features() for r in records]),
-                 ns=np.stack([r.ns_per_slice for r in records]), n_train=args.train)
+                 ns=time_matrix(records, keys), keys=np.array(keys), n_train=args.train)
     return 0
 
 

@@ -25,18 +25,13 @@ def test_learned_predictor_beats_untuned_default(env):
     for k, (n, s, a) in enumerate(train_p + test_p):
         print(f"[gpu] learned timing workload {k} n={n} S={s} a={a:.2f}", flush=True)
         recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=1))
-    sizes = {r.ns_per_slice.size for r in recs}
-    assert len(sizes) == 1                      # the same tuning space for every workload
-    ns = np.stack([r.ns_per_slice for r in recs])
-    assert np.all(ns > 0)
-    rec0 = recon.Reconstruction(64)
-    cur = recon.recon_get_config(rec0.ctx)
-    default_index = [i for i in range(recon.recon_tune_space_size(rec0.ctx))
-                     if (lambda c: (c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags))(
-                         recon.recon_tune_space_config(rec0.ctx, i)) ==
-                     (cur.variant, cur.waves_per_block, cur.inner_chunk, cur.split, cur.slab_flags)][0]
-    rec0.close()
-    res = learned.evaluate(recs[:14], recs[14:], steps=1500, default_index=default_index)
+    for r in recs:
+        assert len(r.keys) == r.ns_per_slice.size and np.all(r.ns_per_slice > 0)
+        assert r.default_key in r.keys                 # the default is a member of the space
+    keys = learned.union_keys(recs)
+    ns = learned.time_matrix(recs, keys)
+    assert np.all(np.isfinite(ns.min(axis=1)))
+    res = learned.evaluate(recs[:14], recs[14:], steps=1500)
     print("   ", res, flush=True)
     assert res["loss_last"] < res["loss_first"]
     # picking by prediction costs no tuning steps and stays near the best

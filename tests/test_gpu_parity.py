@@ -30,19 +30,26 @@ def recon(torch_dev):
     return r
 
 
-VARIANTS = ["naive", "binned", "slab"]
+# "slab" takes the library's default slab configuration (8 waves per
+# work-group, window reads preloaded); "slab11" is the 11-wave instance of
+# the 4x4 window (three waves per SIMD, reads interleaved), which exists for
+# blob radii in [1.5, 2) with table interpolation.
+VARIANTS = ["naive", "binned", "slab", "slab11"]
 
 
-def variant_id(recon, variant):
-    return {"naive": recon.RECON_VARIANT_NAIVE, "binned": recon.RECON_VARIANT_BINNED,
-            "slab": recon.RECON_VARIANT_SLAB}[variant]
+def variant_config(recon, variant):
+    dflt = dict(waves_per_block=0, slab_flags=0)       # 0: the library's default for the variant
+    return {"naive": dict(variant=recon.RECON_VARIANT_NAIVE, **dflt),
+            "binned": dict(variant=recon.RECON_VARIANT_BINNED, **dflt),
+            "slab": dict(variant=recon.RECON_VARIANT_SLAB, **dflt),
+            "slab11": dict(variant=recon.RECON_VARIANT_SLAB, waves_per_block=11, slab_flags=4)}[variant]
 
 
 def gpu_run(recon, torch_dev, n, slices, quats, variant="slab", finalize=True, **params):
     torch, dev = torch_dev
     print(f"[gpu] n={n} S={len(quats)} variant={variant} params={params}", flush=True)
     rec = recon.Reconstruction(n, device=dev, **params)
-    rec.set_config(variant=variant_id(recon, variant))
+    rec.set_config(**variant_config(recon, variant))
     rec.insert(torch.from_numpy(np.ascontiguousarray(slices)).to(dev),
                torch.from_numpy(np.ascontiguousarray(quats)).to(dev))
     V = rec.finalize() if finalize else None
@@ -105,6 +112,12 @@ def test_blob_and_cutoff_variants(recon, torch_dev, variant, a, alpha, m, lerp, 
     params = dict(blob_radius=a, blob_alpha=alpha, blob_order=m, table_lerp=lerp)
     if r_max is not None:
         params["r_max"] = r_max
+    if variant == "slab11" and not (1.5 <= a < 2.0 and lerp):
+        # the 11-wave instance exists only for the 4x4 window with interpolation
+        with pytest.raises(recon.ReconError) as ei:
+            gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, **params)
+        assert ei.value.status == recon.RECON_ECONFIG
+        return
     gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, **params)
     blob = oracle.Blob(a=float(np.float32(a)), alpha=alpha, m=m, N=10000, lerp=bool(lerp))
     ref = oracle_run(w.n, w.slices, w.quats, blob=blob, r_max=r_max)
@@ -203,7 +216,7 @@ def paper_scale():
     return synth.make_workload("paper")
 
 
-@pytest.mark.parametrize("variant", ["binned", "slab"])
+@pytest.mark.parametrize("variant", ["binned", "slab", "slab11"])
 def test_paper_scale_sampled_voxels(recon, torch_dev, paper_scale, variant):
     w = paper_scale
     G, W, V, stats = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)

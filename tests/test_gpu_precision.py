@@ -33,7 +33,7 @@ def run16(env, w, fmt, variant, **params):
     dtype = recon.RECON_SLICE_F16 if fmt == "f16" else recon.RECON_SLICE_BF16
     print(f"[gpu] {fmt} n={w.n} S={w.S} variant={variant}", flush=True)
     rec = recon.Reconstruction(w.n, device=dev, slice_dtype=dtype, **params)
-    rec.set_config(variant={"naive": 1, "binned": 2, "slab": 3}[variant])
+    rec.set_config(variant={"naive": 1, "binned": 2, "slab": 3}[variant], waves_per_block=0, slab_flags=0)
     sl = torch.from_numpy(bits.view(np.int16)).to(dev).view(tdt)
     qt = torch.from_numpy(w.quats).to(dev)
     sc = torch.from_numpy(scales).to(dev) if fmt == "f16" else None

@@ -37,9 +37,10 @@ def test_tuning_space_is_runnable(env):
 
 def test_full_search_keeps_parity_and_selects_best(env):
     torch, dev, recon = env
-    w = synth.make_workload("small", n=32, S=270, K=6, seed_phantom=31, seed_orient=32)
-    rec = recon.Reconstruction(w.n, device=dev, max_batch=2)
+    rec = recon.Reconstruction(32, device=dev, max_batch=2)
     size = recon.recon_tune_space_size(rec.ctx)
+    # one tuning step per call of 2 slices: enough calls to visit the whole space
+    w = synth.make_workload("small", n=32, S=2 * (size + 12), K=6, seed_phantom=31, seed_orient=32)
     print(f"[gpu] tuner: space {size}, {w.S} slices in batches of 2", flush=True)
     recon.recon_tune_begin(rec.ctx, max_steps=0, seed=7)
     rec.insert(torch.from_numpy(w.slices).to(dev), torch.from_numpy(w.quats).to(dev))

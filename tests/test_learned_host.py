@@ -1,0 +1,42 @@
+"""Host logic of the learned configuration predictor (no GPU): configuration
+keys across workloads whose runnable spaces differ, the masked time matrix,
+target distributions, and the regret measures."""
+import numpy as np
+import pytest
+
+from paper_1910_08498_amd import learned
+
+
+def rec(keys, ns, default=None):
+    return learned.TuneRecord(n=64, slices=100, a=1.9, ns_per_slice=np.array(ns, dtype=float), keys=list(keys),
+                              default_key=default)
+
+
+def test_union_keys_and_time_matrix_mask_missing_configs():
+    a = rec([(3, 8, 32, 32, 6), (3, 11, 32, 32, 4)], [2.0, 1.0])
+    b = rec([(3, 8, 32, 32, 6), (2, 16, 32, 32, 6)], [3.0, 6.0])
+    keys = learned.union_keys([a, b])
+    assert keys == [(3, 8, 32, 32, 6), (3, 11, 32, 32, 4), (2, 16, 32, 32, 6)]
+    ns = learned.time_matrix([a, b], keys)
+    assert ns[0].tolist() == [2.0, 1.0, np.inf]
+    assert ns[1].tolist() == [3.0, np.inf, 6.0]
+
+
+def test_soft_targets_give_no_mass_to_configs_that_do_not_run():
+    ns = np.array([[2.0, 1.0, np.inf], [3.0, np.inf, 3.0]])
+    y = learned.soft_targets(ns, temperature=0.02)
+    assert np.allclose(y.sum(axis=1), 1.0)
+    assert y[0, 2] == 0.0 and y[1, 1] == 0.0
+    assert y[0, 1] > 0.999                    # the fastest takes almost all mass
+    assert np.isclose(y[1, 0], 0.5) and np.isclose(y[1, 2], 0.5)
+
+
+def test_regret_and_random_search_use_runnable_configs_only():
+    ns = np.array([[2.0, 1.0, np.inf, 4.0]])
+    assert learned.regret(ns, np.array([1]))[0] == 0.0
+    assert learned.regret(ns, np.array([3]))[0] == pytest.approx(3.0)
+    # a budget covering every runnable configuration always finds the best
+    assert learned.random_search_regret(ns, steps=3, trials=20)[0] == 0.0
+    # one random pick: mean over the three runnable configurations of t / t_best - 1
+    r1 = learned.random_search_regret(ns, steps=1, trials=3000, seed=1)[0]
+    assert r1 == pytest.approx((1.0 + 0.0 + 3.0) / 3, abs=0.1)
