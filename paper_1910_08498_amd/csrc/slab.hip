@@ -90,6 +90,22 @@ __device__ __forceinline__ int wave_min_pk(int v)
                          pk_min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
     return __builtin_amdgcn_readfirstlane(r);
 }
+// Inclusive prefix sum over the 64 lanes (all lanes active): Hillis-Steele
+// steps of 1, 2, 4 and 8 lanes inside each row of 16 (DPP row_shr; lanes
+// shifted in from outside the row add 0), then the last lane of row 0 (and 2)
+// is added to row 1 (and 3) and the last lane of row 1 to rows 2 and 3 (DPP
+// row_bcast:15 and row_bcast:31).
+__device__ __forceinline__ int wave_inclusive_sum(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 __device__ __forceinline__ int pack16(int lo, int hi)
 {
     return static_cast<int>((static_cast<unsigned>(lo) & 0xffffu) | (static_cast<unsigned>(hi) << 16));
@@ -390,20 +406,17 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
                 const float rem = R2 - fmaf(fva, fva, fvb * fvb);
                 const bool col_in = va <= A1 && vb <= B1 && rem >= 0.f;
-                const float lim = sqrtf(fmaxf(rem, 0.f));
+                // hardware square root and reciprocal: R2 and a_run carry far more
+                // slack than their last-bit errors
+                const float lim = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.f));
                 const float q = fmaf(na, fva, nb * fvb);
-                const float inv = 1.0f / nd;
+                const float inv = __builtin_amdgcn_rcpf(nd);
                 const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
                 const int lo = max(static_cast<int>(ceilf(fmaxf(fminf(t1, t2), -lim))), D0);
                 const int hi = min(static_cast<int>(floorf(fminf(fmaxf(t1, t2), lim))), D1);
                 const int cnt = col_in ? max(hi - lo + 1, 0) : 0;
-                int incl = cnt;
-    #pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int y = __shfl_up(incl, off);
-                    if (lane >= off) incl += y;
-                }
-                const int H = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+                const int incl = wave_inclusive_sum(cnt);
+                const int H = __builtin_amdgcn_readlane(incl, 63);
                 st.H = H;
                 if (H == 0) return 0;
                 const int excl = incl - cnt;
@@ -417,19 +430,16 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 // (lanes without hits contribute the neutral 0x7fff; |coordinates|
                 // stay below n / 2 + 8 <= 520, so they fit in int16)
                 int lows = 0x7fff7fff, highs = 0x7fff7fff;
+                // u along the column: u(va, vb) + k e_d for the column's k-th voxel
                 const float e1d = sel3(d, st.e1.x, st.e1.y, st.e1.z);
                 const float e2d = sel3(d, st.e2.x, st.e2.y, st.e2.z);
+                const float e1a = sel3(ia, st.e1.x, st.e1.y, st.e1.z), e1b = sel3(ib, st.e1.x, st.e1.y, st.e1.z);
+                const float e2a = sel3(ia, st.e2.x, st.e2.y, st.e2.z), e2b = sel3(ib, st.e2.x, st.e2.y, st.e2.z);
                 if (cnt > 0) {
-                    const float flo = static_cast<float>(lo);
-                    const float vx0 = d == 0 ? flo : fva;
-                    const float vy0 = d == 1 ? flo : (d == 0 ? fva : fvb);
-                    const float vz0 = d == 2 ? flo : fvb;
-                    const float ux0 = fmaf(st.e1.x, vx0, fmaf(st.e1.y, vy0, st.e1.z * vz0));
-                    const float uy0 = fmaf(st.e2.x, vx0, fmaf(st.e2.y, vy0, st.e2.z * vz0));
-                    // the other end, hi - lo steps along axis d
-                    const float run = static_cast<float>(hi - lo);
-                    const float ux1 = fmaf(run, e1d, ux0);
-                    const float uy1 = fmaf(run, e2d, uy0);
+                    const float uxc = fmaf(e1a, fva, e1b * fvb), uyc = fmaf(e2a, fva, e2b * fvb);
+                    const float flo = static_cast<float>(lo), fhi = static_cast<float>(hi);
+                    const float ux0 = fmaf(flo, e1d, uxc), ux1 = fmaf(fhi, e1d, uxc);
+                    const float uy0 = fmaf(flo, e2d, uyc), uy1 = fmaf(fhi, e2d, uyc);
                     const int xl = static_cast<int>(floorf(fminf(ux0, ux1) - g.a - 1e-3f));
                     const int xh = static_cast<int>(ceilf(fmaxf(ux0, ux1) - g.a + 1e-3f)) + (WIN - 1);
                     const int yl = static_cast<int>(floorf(fminf(uy0, uy1) - g.a - 1e-3f));
@@ -455,7 +465,9 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             auto issue = [&](int s, const Stage &st) {
                 const int wx = st.wx;
                 const int ncell = wx * st.wy;
-                const float inv_wx = 1.0f / static_cast<float>(wx);
+                // (c + 1/2) / wx stays at least 1 / (2 wx) away from an integer, far
+                // above the hardware reciprocal's error
+                const float inv_wx = __builtin_amdgcn_rcpf(static_cast<float>(wx));
                 // buffer resource over this slice: 32-bit offsets, hardware bounds check
                 // (reads at or past the record size return zero: cells outside
                 // the disk are loaded from there and so stage as zero)
