@@ -205,7 +205,7 @@ recon_config default_config()
     c.waves_per_block = 8;
     c.group = 1;
     c.inner_chunk = 32;
-    c.split = 32;
+    c.split = 16;
     c.slab_flags = 4 | 2;
     return c;
 }

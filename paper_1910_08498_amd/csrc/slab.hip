@@ -73,23 +73,37 @@ __device__ __forceinline__ void wave_sync()
 
 // Componentwise minimum over the 64 lanes of a wavefront (all lanes active)
 // of two int16 values packed in one register: DPP permutations reduce each
-// row of 16 lanes, then the four row results are combined.
+// row of 16 lanes, then row broadcasts carry rows 0-2 into row 3, whose last
+// lane holds the result.
 typedef short short2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ int pk_min(int a, int b)
 {
     return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(short2_t, a),
                                                              __builtin_bit_cast(short2_t, b)));
 }
-__device__ __forceinline__ int wave_min_pk(int v)
+// Two such reductions run interleaved, so each DPP step's wait for its
+// source overlaps the other's.  The quad and mirror steps read valid lanes
+// only (no fill value needed); the row broadcasts leave rows outside their
+// mask at the neutral value.
+__device__ __forceinline__ void wave_min_pk2(int &a, int &b)
 {
-    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
-    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
-    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
-    v = pk_min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
-    const int r = pk_min(pk_min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-                         pk_min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-    return __builtin_amdgcn_readfirstlane(r);
+    constexpr int NEUTRAL = 0x7fff7fff;
+    a = pk_min(a, __builtin_amdgcn_mov_dpp(a, 0xB1, 0xF, 0xF, false));            // quad_perm [1,0,3,2]
+    b = pk_min(b, __builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, false));
+    a = pk_min(a, __builtin_amdgcn_mov_dpp(a, 0x4E, 0xF, 0xF, false));            // quad_perm [2,3,0,1]
+    b = pk_min(b, __builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, false));
+    a = pk_min(a, __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, false));           // row_half_mirror
+    b = pk_min(b, __builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, false));
+    a = pk_min(a, __builtin_amdgcn_mov_dpp(a, 0x140, 0xF, 0xF, false));           // row_mirror
+    b = pk_min(b, __builtin_amdgcn_mov_dpp(b, 0x140, 0xF, 0xF, false));
+    a = pk_min(a, __builtin_amdgcn_update_dpp(NEUTRAL, a, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    b = pk_min(b, __builtin_amdgcn_update_dpp(NEUTRAL, b, 0x142, 0xA, 0xF, false));
+    a = pk_min(a, __builtin_amdgcn_update_dpp(NEUTRAL, a, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    b = pk_min(b, __builtin_amdgcn_update_dpp(NEUTRAL, b, 0x143, 0xC, 0xF, false));
+    a = __builtin_amdgcn_readlane(a, 63);
+    b = __builtin_amdgcn_readlane(b, 63);
 }
+
 // Inclusive prefix sum over the 64 lanes (all lanes active): Hillis-Steele
 // steps of 1, 2, 4 and 8 lanes inside each row of 16 (DPP row_shr; lanes
 // shifted in from outside the row add 0), then the last lane of row 0 (and 2)
@@ -113,13 +127,12 @@ __device__ __forceinline__ int pack16(int lo, int hi)
 __device__ __forceinline__ int unpack16_lo(int v) { return static_cast<short>(v & 0xffff); }
 __device__ __forceinline__ int unpack16_hi(int v) { return v >> 16; }
 
-__device__ __forceinline__ float uniformf(float x)
+// The same global buffer seen through the constant address space: loads
+// with a wave-uniform index become scalar loads into scalar registers.
+template <typename T>
+__device__ __forceinline__ const T __attribute__((address_space(4))) *const_space(const T *p)
 {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-__device__ __forceinline__ float4 uniform4(float4 v)
-{
-    return make_float4(uniformf(v.x), uniformf(v.y), uniformf(v.z), uniformf(v.w));
+    return (const T __attribute__((address_space(4))) *)reinterpret_cast<unsigned long long>(p);
 }
 
 __device__ __forceinline__ float sel3(int i, float x, float y, float z)
@@ -369,13 +382,15 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             int dst[NC];
 
             auto setup = [&](int s, Stage &st) {
-                // s is wave-uniform: the orientation and scale go to scalar
-                // registers, so no later copy of the stage waits on sample loads
-                const Orient ov = orient[s];
-                st.e1 = uniform4(ov.e1);
-                st.e2 = uniform4(ov.e2);
-                st.e3 = uniform4(ov.e3);
-                st.scale = g.scales ? uniformf(g.scales[s]) : 1.0f;
+                // s is wave-uniform: the orientation and scale are read with scalar
+                // loads (constant address space) straight into scalar registers, so
+                // no later copy of the stage waits on the sample loads
+                const float __attribute__((address_space(4))) *o =
+                    const_space(reinterpret_cast<const float *>(orient)) + static_cast<long>(s) * (sizeof(Orient) / 4);
+                st.e1 = make_float4(o[0], o[1], o[2], o[3]);
+                st.e2 = make_float4(o[4], o[5], o[6], o[7]);
+                st.e3 = make_float4(o[8], o[9], o[10], o[11]);
+                st.scale = g.scales ? const_space(g.scales)[s] : 1.0f;
             };
 
             // (1) Voxels inside the slab |e3.v| <= a (and inside the reach sphere
@@ -425,30 +440,27 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
 #pragma unroll
                 for (int k = 0; k < TE; ++k)
                     if (k < cnt) lst[excl + k] = static_cast<unsigned short>(lid0 + k * sd);
-                // in-plane coordinates of the run's end voxels, computed as the
-                // windows compute them
-                // (lanes without hits contribute the neutral 0x7fff; |coordinates|
-                // stay below n / 2 + 8 <= 520, so they fit in int16)
-                int lows = 0x7fff7fff, highs = 0x7fff7fff;
-                // u along the column: u(va, vb) + k e_d for the column's k-th voxel
+                // Bounds of the hits' windows from the ends of each column's run: u
+                // along a column is u(va, vb) + k e_d, and the 1e-3 slack covers the
+                // rounding against the windows' own evaluation.  Every lane computes;
+                // columns without hits give the neutral 0x7fff.  |coordinates| stay
+                // below n / 2 + 8 <= 520, so they fit in int16.
                 const float e1d = sel3(d, st.e1.x, st.e1.y, st.e1.z);
                 const float e2d = sel3(d, st.e2.x, st.e2.y, st.e2.z);
                 const float e1a = sel3(ia, st.e1.x, st.e1.y, st.e1.z), e1b = sel3(ib, st.e1.x, st.e1.y, st.e1.z);
                 const float e2a = sel3(ia, st.e2.x, st.e2.y, st.e2.z), e2b = sel3(ib, st.e2.x, st.e2.y, st.e2.z);
-                if (cnt > 0) {
-                    const float uxc = fmaf(e1a, fva, e1b * fvb), uyc = fmaf(e2a, fva, e2b * fvb);
-                    const float flo = static_cast<float>(lo), fhi = static_cast<float>(hi);
-                    const float ux0 = fmaf(flo, e1d, uxc), ux1 = fmaf(fhi, e1d, uxc);
-                    const float uy0 = fmaf(flo, e2d, uyc), uy1 = fmaf(fhi, e2d, uyc);
-                    const int xl = static_cast<int>(floorf(fminf(ux0, ux1) - g.a - 1e-3f));
-                    const int xh = static_cast<int>(ceilf(fmaxf(ux0, ux1) - g.a + 1e-3f)) + (WIN - 1);
-                    const int yl = static_cast<int>(floorf(fminf(uy0, uy1) - g.a - 1e-3f));
-                    const int yh = static_cast<int>(ceilf(fmaxf(uy0, uy1) - g.a + 1e-3f)) + (WIN - 1);
-                    lows = pack16(xl, yl);
-                    highs = pack16(-xh, -yh);
-                }
-                lows = wave_min_pk(lows);
-                highs = wave_min_pk(highs);
+                const float am = g.a + 1e-3f, ap = g.a - 1e-3f;
+                const float uxc = fmaf(e1a, fva, e1b * fvb), uyc = fmaf(e2a, fva, e2b * fvb);
+                const float flo = static_cast<float>(lo), fhi = static_cast<float>(hi);
+                const float ux0 = fmaf(flo, e1d, uxc), ux1 = fmaf(fhi, e1d, uxc);
+                const float uy0 = fmaf(flo, e2d, uyc), uy1 = fmaf(fhi, e2d, uyc);
+                const int xl = static_cast<int>(floorf(fminf(ux0, ux1) - am));
+                const int xh = static_cast<int>(ceilf(fmaxf(ux0, ux1) - ap)) + (WIN - 1);
+                const int yl = static_cast<int>(floorf(fminf(uy0, uy1) - am));
+                const int yh = static_cast<int>(ceilf(fmaxf(uy0, uy1) - ap)) + (WIN - 1);
+                int lows = cnt > 0 ? pack16(xl, yl) : 0x7fff7fff;
+                int highs = cnt > 0 ? pack16(-xh, -yh) : 0x7fff7fff;
+                wave_min_pk2(lows, highs);
                 st.kx_lo = unpack16_lo(lows);
                 st.ky_lo = unpack16_hi(lows);
                 // never wider than RECT; min() only guards the buffer
