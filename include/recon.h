@@ -84,10 +84,14 @@ typedef enum recon_variant {
  * "library default".  Invalid combinations are rejected with RECON_ECONFIG. */
 typedef struct recon_config {
     int32_t variant;          /* recon_variant */
-    int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8, 12 or 16 */
+    int32_t waves_per_block;  /* wavefronts per work-group: 1, 2, 4, 8, 12 or 16; the slab
+                                 variant runs 4 or 8, or 11 (three waves per SIMD, window
+                                 reads never preloaded; the default where it exists) for
+                                 blob radii in [1.5, 2) with table interpolation */
     int32_t group;            /* slices staged per LDS group (binned): 1..16 */
     int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 */
-    int32_t split;            /* max slice-range splits of one tile (binned, slab): 1..64 */
+    int32_t split;            /* max slice-range splits of one tile (binned, slab): 1..64
+                                 (default 16) */
     int32_t slab_flags;       /* slab variant, 4 | bits: bit 0 LDS float atomics for the
                                  accumulators, bit 1 issue all window reads before use
                                  (default 4 | 2) */

@@ -106,7 +106,7 @@ hipError_t launch_zero(float *p, size_t count, hipStream_t st)
 // ---------------------------------------------------------------------------
 // orientation prep: quaternion (w, x, y, z) -> columns of R, in FP32
 // ---------------------------------------------------------------------------
-__global__ void k_prep(const float4 *__restrict__ quats, int count, Orient *__restrict__ orient,
+__global__ void k_prep(const float4 *__restrict__ quats, int count, float tscale, Orient *__restrict__ orient,
                        Counters *__restrict__ ctr, unsigned *__restrict__ queue)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -120,7 +120,7 @@ __global__ void k_prep(const float4 *__restrict__ quats, int count, Orient *__re
     Orient o;
     if (!(nn > 0.0f) || !isfinite(nn)) {
         o.e1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        o.e2 = o.e3 = o.pad = o.e1;
+        o.e2 = o.e3 = o.e1s = o.e2s = o.e3s = o.p1 = o.p2 = o.e1;
         orient[s] = o;
         atomicAdd(&ctr->rejected, 1ull);
         return;
@@ -133,16 +133,29 @@ __global__ void k_prep(const float4 *__restrict__ quats, int count, Orient *__re
     o.e1 = make_float4(1.f - 2.f * (y * y + z * z), 2.f * (x * y + w * z), 2.f * (x * z - w * y), 1.f);
     o.e2 = make_float4(2.f * (x * y - w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z + w * x), 0.f);
     o.e3 = make_float4(2.f * (x * z + w * y), 2.f * (y * z - w * x), 1.f - 2.f * (x * x + y * y), 0.f);
-    o.pad = make_float4(0.f, 0.f, 0.f, 0.f);
+    // slab-kernel constants
+    const float r = sqrtf(tscale);
+    const float n[3] = {o.e3.x, o.e3.y, o.e3.z};
+    const float a1[3] = {o.e1.x, o.e1.y, o.e1.z};
+    const float a2[3] = {o.e2.x, o.e2.y, o.e2.z};
+    const float m0 = fabsf(n[0]), m1 = fabsf(n[1]), m2 = fabsf(n[2]);
+    const int d = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
+    const int ia = d == 0 ? 1 : 0;
+    const int ib = d == 2 ? 1 : 2;
+    o.e1s = make_float4(r * o.e1.x, r * o.e1.y, r * o.e1.z, __int_as_float(d | (ia << 8) | (ib << 16)));
+    o.e2s = make_float4(r * o.e2.x, r * o.e2.y, r * o.e2.z, 1.0f / n[d]);
+    o.e3s = make_float4(r * o.e3.x, r * o.e3.y, r * o.e3.z, n[d]);
+    o.p1 = make_float4(a1[d], a1[ia], a1[ib], n[ia]);
+    o.p2 = make_float4(a2[d], a2[ia], a2[ib], n[ib]);
     orient[s] = o;
 }
 
-hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr, unsigned *queue,
+hipError_t launch_prep(const float *quats, int count, float tscale, Orient *orient, Counters *ctr, unsigned *queue,
                        hipStream_t st)
 {
     const int blocks = count > 0 ? (count + 255) / 256 : 1;
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st,
-                       reinterpret_cast<const float4 *>(quats), count, orient, ctr, queue);
+                       reinterpret_cast<const float4 *>(quats), count, tscale, orient, ctr, queue);
     return hipGetLastError();
 }
 

@@ -40,11 +40,21 @@ __device__ __forceinline__ float2 decode_sample(const unsigned char *__restrict_
     return make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
 }
 
-// Per-slice orientation record written by the prep kernel (64 bytes).
+// Per-slice orientation record written by the prep kernel (128 bytes).
 // e1, e2 are the images of the slice's x and y axes in the volume, e3 the
 // plane normal (columns of R).  e1.w is 1 for a usable slice, 0 otherwise.
+// The rest are per-slice constants of the slab kernel, computed once here
+// instead of once per (tile, slice):
+//   e1s, e2s, e3s  the axes scaled by sqrt((N-1)/a^2) (table units);
+//   e1s.w          the axes' order as int bits d | ia << 8 | ib << 16: d is
+//                  e3's dominant axis, ia < ib the other two;
+//   e2s.w          1 / e3[d];  e3s.w  e3[d];
+//   p1, p2         (e[d], e[ia], e[ib], .) of e1 and e2; p1.w = e3[ia],
+//                  p2.w = e3[ib].
 struct Orient {
-    float4 e1, e2, e3, pad;
+    float4 e1, e2, e3;
+    float4 e1s, e2s, e3s;
+    float4 p1, p2;
 };
 
 // Workspace counters (device, 256 bytes at the start of the workspace).
@@ -85,7 +95,7 @@ struct JobTable {
 hipError_t launch_zero(float *p, size_t count, hipStream_t st);
 // Orientation records for a batch; adds `count` to ctr->inserted; zeroes
 // *queue (a work-queue head) when given.
-hipError_t launch_prep(const float *quats, int count, Orient *orient, Counters *ctr, unsigned *queue,
+hipError_t launch_prep(const float *quats, int count, float tscale, Orient *orient, Counters *ctr, unsigned *queue,
                        hipStream_t st);
 hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices,
                                const Orient *orient, int count, const float2 *table,

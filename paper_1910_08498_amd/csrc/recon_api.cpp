@@ -365,6 +365,12 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->g.r2max = p->r_max * p->r_max;
     c->g.dtype = p->slice_dtype;
     c->g.scales = nullptr;
+    if (slab_wide_ok(c->g, p->table_lerp != 0, c->max_lds)) {
+        // three waves per SIMD where the 11-wave instance applies (the
+        // fastest measured configuration for the 4 x 4 window)
+        c->cfg.waves_per_block = 11;
+        c->cfg.slab_flags = 4;
+    }
     if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
         // blob table too large for the slab kernel's LDS budget
         c->cfg.variant = static_cast<size_t>(p->table_size) * sizeof(float2) <= c->max_lds ? RECON_VARIANT_BINNED
@@ -455,7 +461,7 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     Orient *orient = reinterpret_cast<Orient *>(c->ws + c->L.orient);
     const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
     const void *slices = d_slices;
-    hipError_t e = recon::launch_prep(d_quats, count, orient, ctr, &ctr->queue, c->stream);
+    hipError_t e = recon::launch_prep(d_quats, count, c->g.tscale, orient, ctr, &ctr->queue, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
     if (c->ev_start) {
         e = hipEventRecord(c->ev_start, c->stream);
@@ -533,7 +539,7 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     recon_config n = cfg ? *cfg : d;
     if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
     const bool wide = n.variant == RECON_VARIANT_SLAB && slab_wide_ok(c->g, c->p.table_lerp != 0, c->max_lds);
-    if (n.waves_per_block == 0) n.waves_per_block = default_waves(n.variant);
+    if (n.waves_per_block == 0) n.waves_per_block = wide ? 11 : default_waves(n.variant);
     if (n.slab_flags == 0 && n.waves_per_block == 11) n.slab_flags = 4;
     if (n.group == 0) n.group = d.group;
     if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
@@ -906,7 +912,7 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     for (int j = 0; j < nj; ++j) {
         recon_ctx *c = b->ctxs[j];
         if (counts[j] == 0 && j != 0) continue;
-        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j],
+        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j], c->g.tscale,
                                           reinterpret_cast<Orient *>(c->ws + c->L.orient),
                                           reinterpret_cast<Counters *>(c->ws + c->L.ctr),
                                           j == 0 ? &bctr->queue : nullptr, st);

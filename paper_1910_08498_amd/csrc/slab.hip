@@ -135,10 +135,6 @@ __device__ __forceinline__ const T __attribute__((address_space(4))) *const_spac
     return (const T __attribute__((address_space(4))) *)reinterpret_cast<unsigned long long>(p);
 }
 
-__device__ __forceinline__ float sel3(int i, float x, float y, float z)
-{
-    return i == 0 ? x : (i == 1 ? y : z);
-}
 __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 {
     return i == 0 ? x : (i == 1 ? y : z);
@@ -368,7 +364,8 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             // (4), so its loads are in flight while these windows are evaluated
             // (two hit lists alternate).
             struct Stage {
-                float4 e1, e2, e3;
+                float4 e1s, e2s, e3s;        // axes in table units; .w: axis order, 1/e3[d], e3[d]
+                float4 p1, p2;               // e1, e2 along (d, ia, ib); .w: e3[ia], e3[ib]
                 int kx_lo, ky_lo, wx, wy;    // staged rectangle: columns kx_lo.., rows ky_lo..
                 int rim;                     // int, not bool: no padding bytes in the struct copies
                 int H;                       // hits
@@ -385,11 +382,14 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 // s is wave-uniform: the orientation and scale are read with scalar
                 // loads (constant address space) straight into scalar registers, so
                 // no later copy of the stage waits on the sample loads
+                // (the slab kernel's per-slice constants, words 12..31 of the record)
                 const float __attribute__((address_space(4))) *o =
                     const_space(reinterpret_cast<const float *>(orient)) + static_cast<long>(s) * (sizeof(Orient) / 4);
-                st.e1 = make_float4(o[0], o[1], o[2], o[3]);
-                st.e2 = make_float4(o[4], o[5], o[6], o[7]);
-                st.e3 = make_float4(o[8], o[9], o[10], o[11]);
+                st.e1s = make_float4(o[12], o[13], o[14], o[15]);
+                st.e2s = make_float4(o[16], o[17], o[18], o[19]);
+                st.e3s = make_float4(o[20], o[21], o[22], o[23]);
+                st.p1 = make_float4(o[24], o[25], o[26], o[27]);
+                st.p2 = make_float4(o[28], o[29], o[30], o[31]);
                 st.scale = g.scales ? const_space(g.scales)[s] : 1.0f;
             };
 
@@ -401,15 +401,10 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             // of slack for rounding (u is linear along a run, so the run's end
             // voxels bound it).  Returns the hit count.
             auto enumerate = [&](Stage &st, unsigned short *lst) -> int {
-                const float4 e3 = st.e3;
-                const float n0 = fabsf(e3.x), n1 = fabsf(e3.y), n2 = fabsf(e3.z);
-                // (a scalar: selections on d below stay scalar)
-                const int d = __builtin_amdgcn_readfirstlane((n0 >= n1 && n0 >= n2) ? 0 : (n1 >= n2 ? 1 : 2));
-                const int ia = d == 0 ? 1 : 0;
-                const int ib = d == 2 ? 1 : 2;
-                const float nd = sel3(d, e3.x, e3.y, e3.z);
-                const float na = sel3(ia, e3.x, e3.y, e3.z);
-                const float nb = sel3(ib, e3.x, e3.y, e3.z);
+                // axis order and normal components, precomputed per slice
+                const int axes = __float_as_int(st.e1s.w);
+                const int d = axes & 0xff, ia = (axes >> 8) & 0xff, ib = axes >> 16;
+                const float na = st.p1.w, nb = st.p2.w;
                 const int D0 = sel3i(d, X0, Y0, Z0), D1 = sel3i(d, X1, Y1, Z1);
                 const int A0 = sel3i(ia, X0, Y0, Z0), A1 = sel3i(ia, X1, Y1, Z1);
                 const int B0 = sel3i(ib, X0, Y0, Z0), B1 = sel3i(ib, X1, Y1, Z1);
@@ -421,11 +416,11 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
                 const float rem = R2 - fmaf(fva, fva, fvb * fvb);
                 const bool col_in = va <= A1 && vb <= B1 && rem >= 0.f;
-                // hardware square root and reciprocal: R2 and a_run carry far more
-                // slack than their last-bit errors
+                // hardware square root: R2 carries far more slack than its last-bit
+                // error
                 const float lim = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.f));
                 const float q = fmaf(na, fva, nb * fvb);
-                const float inv = __builtin_amdgcn_rcpf(nd);
+                const float inv = st.e2s.w;                  // 1 / e3[d]
                 const float t1 = (-a_run - q) * inv, t2 = (a_run - q) * inv;
                 const int lo = max(static_cast<int>(ceilf(fmaxf(fminf(t1, t2), -lim))), D0);
                 const int hi = min(static_cast<int>(floorf(fminf(fmaxf(t1, t2), lim))), D1);
@@ -445,10 +440,8 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 // rounding against the windows' own evaluation.  Every lane computes;
                 // columns without hits give the neutral 0x7fff.  |coordinates| stay
                 // below n / 2 + 8 <= 520, so they fit in int16.
-                const float e1d = sel3(d, st.e1.x, st.e1.y, st.e1.z);
-                const float e2d = sel3(d, st.e2.x, st.e2.y, st.e2.z);
-                const float e1a = sel3(ia, st.e1.x, st.e1.y, st.e1.z), e1b = sel3(ib, st.e1.x, st.e1.y, st.e1.z);
-                const float e2a = sel3(ia, st.e2.x, st.e2.y, st.e2.z), e2b = sel3(ib, st.e2.x, st.e2.y, st.e2.z);
+                const float e1d = st.p1.x, e1a = st.p1.y, e1b = st.p1.z;
+                const float e2d = st.p2.x, e2a = st.p2.y, e2b = st.p2.z;
                 const float am = g.a + 1e-3f, ap = g.a - 1e-3f;
                 const float uxc = fmaf(e1a, fva, e1b * fvb), uyc = fmaf(e2a, fva, e2b * fvb);
                 const float flo = static_cast<float>(lo), fhi = static_cast<float>(hi);
@@ -568,10 +561,8 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
 
                 // (4) windows of the hits, 64 per round
                 const int H = cur.H;
-                // orientation scaled by s: coordinates in table units
-                const float4 e1s = make_float4(cur.e1.x * ts_root, cur.e1.y * ts_root, cur.e1.z * ts_root, 0.f);
-                const float4 e2s = make_float4(cur.e2.x * ts_root, cur.e2.y * ts_root, cur.e2.z * ts_root, 0.f);
-                const float4 e3s = make_float4(cur.e3.x * ts_root, cur.e3.y * ts_root, cur.e3.z * ts_root, 0.f);
+                // slice axes in table units
+                const float4 e1s = cur.e1s, e2s = cur.e2s, e3s = cur.e3s;
                 for (int r = 0; r < H; r += 64) {
                     const int hh = r + lane;
                     if (hh < H) {

@@ -30,11 +30,12 @@ def recon(torch_dev):
     return r
 
 
-# "slab" takes the library's default slab configuration (8 waves per
-# work-group, window reads preloaded); "slab11" is the 11-wave instance of
-# the 4x4 window (three waves per SIMD, reads interleaved), which exists for
-# blob radii in [1.5, 2) with table interpolation.
-VARIANTS = ["naive", "binned", "slab", "slab11"]
+# "slab" takes the library's default slab configuration (11 waves per
+# work-group, three per SIMD, for the 4x4 window with table interpolation;
+# 8 waves with window reads preloaded otherwise); "slab8" is the 8-wave
+# preloading instance, "slab11" the 11-wave one (which exists for blob radii
+# in [1.5, 2) with table interpolation only).
+VARIANTS = ["naive", "binned", "slab", "slab8", "slab11"]
 
 
 def variant_config(recon, variant):
@@ -42,6 +43,7 @@ def variant_config(recon, variant):
     return {"naive": dict(variant=recon.RECON_VARIANT_NAIVE, **dflt),
             "binned": dict(variant=recon.RECON_VARIANT_BINNED, **dflt),
             "slab": dict(variant=recon.RECON_VARIANT_SLAB, **dflt),
+            "slab8": dict(variant=recon.RECON_VARIANT_SLAB, waves_per_block=8, slab_flags=6),
             "slab11": dict(variant=recon.RECON_VARIANT_SLAB, waves_per_block=11, slab_flags=4)}[variant]
 
 
@@ -216,7 +218,7 @@ def paper_scale():
     return synth.make_workload("paper")
 
 
-@pytest.mark.parametrize("variant", ["binned", "slab", "slab11"])
+@pytest.mark.parametrize("variant", ["binned", "slab", "slab8"])
 def test_paper_scale_sampled_voxels(recon, torch_dev, paper_scale, variant):
     w = paper_scale
     G, W, V, stats = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)
