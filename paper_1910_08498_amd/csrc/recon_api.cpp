@@ -370,6 +370,8 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
         // fastest measured configuration for the 4 x 4 window)
         c->cfg.waves_per_block = 11;
         c->cfg.slab_flags = 4;
+        c->cfg.inner_chunk = 64;
+        c->cfg.split = 64;
     }
     if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
         // blob table too large for the slab kernel's LDS budget

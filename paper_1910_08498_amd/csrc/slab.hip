@@ -158,16 +158,16 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
     const float fx0 = ceilf(fmaf(uxs, inv_s, -g.a));
     const float fy0 = ceilf(fmaf(uys, inv_s, -g.a));
     // the staged rectangle holds every window; the clamp only guards the buffer
-    const int off = min(max((static_cast<int>(fy0) - ky_lo) * RECT + (static_cast<int>(fx0) - kx_lo), 0), MAXOFF);
+    const int off = min(max(__mul24(static_cast<int>(fy0) - ky_lo, RECT) + (static_cast<int>(fx0) - kx_lo), 0), MAXOFF);
     const float2 *base = rect + off;
     float dxs[WIN], dys[WIN];
     const float dx0 = fmaf(-s, fx0, uxs), dy0 = fmaf(-s, fy0, uys);
     const float uz2 = uzs * uzs;
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {
-        const float dx = fmaf(-s, static_cast<float>(i), dx0);
+        const float dx = i == 0 ? dx0 : fmaf(-s, static_cast<float>(i), dx0);
         dxs[i] = dx * dx;
-        const float dy = fmaf(-s, static_cast<float>(i), dy0);
+        const float dy = i == 0 ? dy0 : fmaf(-s, static_cast<float>(i), dy0);
         dys[i] = fmaf(dy, dy, uz2);
     }
     float sr = 0.f, si = 0.f, sw = 0.f;
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 st.H = H;
                 if (H == 0) return 0;
                 const int excl = incl - cnt;
-                const int lid0 = ca * sa + cb * sb + (lo - D0) * sd;
+                const int lid0 = __mul24(ca, sa) + __mul24(cb, sb) + __mul24(lo - D0, sd);
                 // a run never exceeds the tile edge: a fixed, predicated loop
 #pragma unroll
                 for (int k = 0; k < TE; ++k)
@@ -490,13 +490,14 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                     const int cy_ = static_cast<int>((static_cast<float>(c) + 0.5f) * inv_wx);
                     const int cx_ = c - cy_ * wx;
                     const int kx = st.kx_lo + cx_, ky = st.ky_lo + cy_;
-                    const bool valid = c < ncell && static_cast<float>(kx * kx + ky * ky) < g.r2max;
+                    // (operands below 2^11: 24-bit multiplies run at full rate)
+                    const bool valid = c < ncell && static_cast<float>(__mul24(kx, kx) + __mul24(ky, ky)) < g.r2max;
                     const bool direct = kx > 0 || (kx == 0 && ky >= 0);
                     const int row = direct ? ky + g.h : g.h - ky;
                     const int col = direct ? kx : -kx;
-                    off[qq] = valid ? (row * g.sw + col) * eb : bytes;
+                    off[qq] = valid ? (__mul24(row, g.sw) + col) * eb : bytes;
                     // the sign flip of mirrored samples is applied at commit
-                    dst[qq] = c < ncell ? (direct ? 1 : -1) * (cy_ * RECT + cx_ + 1) : 0;
+                    dst[qq] = c < ncell ? (direct ? 1 : -1) * (__mul24(cy_, RECT) + cx_ + 1) : 0;
                 }
                 // all loads back to back; only as many as the rectangle needs
                 // (st.nq is wave-uniform)
