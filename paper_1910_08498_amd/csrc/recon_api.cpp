@@ -142,10 +142,12 @@ Plan make_plan(const recon_params &p, int split, int E)
                 tiles.push_back({tx + TX * (ty + TY * tz), cost});
                 total += cost;
             }
-    // target item cost: a quarter of the mean cost per wavefront slot of a
-    // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits
+    // target item cost: an eighth of the mean cost per wavefront slot of a
+    // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits:
+    // the persistent waves pull items largest first, and small items keep the
+    // tail of the launch short (a quarter measured 5 % slower)
     const double slots = 256.0 * (E == 4 ? 16.0 : 8.0);
-    const double target = std::max(24.0, total / (slots * 4.0));
+    const double target = std::max(24.0, total / (slots * 8.0));
     struct Tmp { Item it; double cost; };
     std::vector<Tmp> tmp;
     for (const Est &e : tiles) {
