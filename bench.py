@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 PEAK_HBM_GBPS = 8000.0        # MI355X HBM3E (published)
 FLOPS_PER_UPDATE = 10         # essential: 5 for d^2, 2 FMA + 1 add for G.re, G.im, W
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1910_08498_amd", "csrc", f) for f in ("kernels.hip", "slab.hip")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1910_08498_amd", "csrc", f)
+               for f in ("kernels.hip", "slab.hip", "recon_api.cpp")]   # kernels and their work plan
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "insert_slab_paper_traffic.json")
 
 WORKLOAD_TEXT = {

@@ -36,7 +36,7 @@ namespace {
 
 constexpr int TE = 8;                  // tile edge
 constexpr int TV = TE * TE * TE;       // voxels per tile
-constexpr int ACC_WORDS = 3 * TV;      // re[512], im[512], w[512]
+constexpr int ACC_WORDS = 3 * TV;      // (re, im) pairs [512], then w [512]
 constexpr int LIST_WORDS = TV / 2;     // 512 uint16 voxel ids
 
 // The staged rectangle spans columns floor(u_min - a - 1e-3) to
