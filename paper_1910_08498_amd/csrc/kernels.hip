@@ -106,9 +106,70 @@ hipError_t launch_zero(float *p, size_t count, hipStream_t st)
 // ---------------------------------------------------------------------------
 // orientation prep: quaternion (w, x, y, z) -> columns of R, in FP32
 // ---------------------------------------------------------------------------
-__global__ void k_prep(const float4 *__restrict__ quats, int count, float tscale, Orient *__restrict__ orient,
-                       Counters *__restrict__ ctr, unsigned *__restrict__ queue)
+// R is formed in double-float arithmetic (a value is the unevaluated sum
+// hi + lo of two floats: error-free two-sum and fma two-product, about 44
+// bits) and rounded to FP32 once, so every stored axis component is the
+// exact rotation of the given FP32 quaternion, correctly rounded.  Plain FP32
+// evaluation loses a few bits per component, and the position error it
+// causes grows with the distance from the origin (at |v| = 500 it dominates
+// the geometry error of a window).  Contraction is off in these helpers and
+// in the prep kernel: a product fused into a following sum after inlining
+// would break the error-free transformations.
+struct DF {
+    float hi, lo;
+};
+__device__ __forceinline__ DF df_quick(float a, float b)   // |a| >= |b| or a == 0
 {
+#pragma clang fp contract(off)
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ DF df_sum(float a, float b)
+{
+#pragma clang fp contract(off)
+    const float s = a + b;
+    const float bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DF df_prod(float a, float b)
+{
+#pragma clang fp contract(off)
+    const float p = a * b;
+    return {p, fmaf(a, b, -p)};
+}
+__device__ __forceinline__ DF df_add(DF a, DF b)
+{
+#pragma clang fp contract(off)
+    DF s = df_sum(a.hi, b.hi);
+    const DF t = df_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = df_quick(s.hi, s.lo);
+    s.lo += t.lo;
+    return df_quick(s.hi, s.lo);
+}
+__device__ __forceinline__ DF df_neg(DF a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ DF df_scale(DF a, float b)
+{
+#pragma clang fp contract(off)
+    DF p = df_prod(a.hi, b);
+    p.lo = fmaf(a.lo, b, p.lo);
+    return df_quick(p.hi, p.lo);
+}
+// a / b for b > 0: quotient of the leading parts, then one correction from
+// the remainder
+__device__ __forceinline__ DF df_div(DF a, DF b)
+{
+#pragma clang fp contract(off)
+    const float q1 = a.hi / b.hi;
+    const DF r = df_add(a, df_neg(df_scale(b, q1)));
+    return df_quick(q1, r.hi / b.hi);
+}
+
+__global__ void k_prep(const float4 *__restrict__ quats, int count, float tscale, int exact,
+                       Orient *__restrict__ orient, float4 *__restrict__ rem, Counters *__restrict__ ctr,
+                       unsigned *__restrict__ queue)
+{
+#pragma clang fp contract(off)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
         if (queue) *queue = 0u;
@@ -125,15 +186,29 @@ __global__ void k_prep(const float4 *__restrict__ quats, int count, float tscale
         atomicAdd(&ctr->rejected, 1ull);
         return;
     }
-    const float inv = 1.0f / sqrtf(nn);
-    const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
-    // R = [[1-2(y2+z2), 2(xy-wz), 2(xz+wy)],
-    //      [2(xy+wz), 1-2(x2+z2), 2(yz-wx)],
-    //      [2(xz-wy), 2(yz+wx), 1-2(x2+y2)]]   (Hamilton, active rotation)
-    o.e1 = make_float4(1.f - 2.f * (y * y + z * z), 2.f * (x * y + w * z), 2.f * (x * z - w * y), 1.f);
-    o.e2 = make_float4(2.f * (x * y - w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z + w * x), 0.f);
-    o.e3 = make_float4(2.f * (x * z + w * y), 2.f * (y * z - w * x), 1.f - 2.f * (x * x + y * y), 0.f);
-    // slab-kernel constants
+    // R(q) = M(q) / |q|^2 for the unnormalised q (Hamilton, active rotation):
+    //   M = [[ww+xx-yy-zz, 2(xy-wz),    2(xz+wy)],
+    //        [2(xy+wz),    ww-xx+yy-zz, 2(yz-wx)],
+    //        [2(xz-wy),    2(yz+wx),    ww-xx-yy+zz]]
+    // which equals the normalised form 1 - 2(y^2 + z^2), ... exactly.
+    const float w = q.x, x = q.y, y = q.z, z = q.w;
+    const DF ww = df_prod(w, w), xx = df_prod(x, x), yy = df_prod(y, y), zz = df_prod(z, z);
+    const DF xy = df_prod(x, y), wz = df_prod(w, z), xz = df_prod(x, z), wy = df_prod(w, y);
+    const DF yz = df_prod(y, z), wx = df_prod(w, x);
+    const DF n2 = df_add(df_add(ww, xx), df_add(yy, zz));
+    // the factor 2 of the off-diagonal terms is exact in any precision
+    auto ent = [&](DF m, float two) { return df_div(df_scale(m, two), n2); };
+    const DF r00 = ent(df_add(df_add(ww, xx), df_neg(df_add(yy, zz))), 1.f);
+    const DF r11 = ent(df_add(df_add(ww, yy), df_neg(df_add(xx, zz))), 1.f);
+    const DF r22 = ent(df_add(df_add(ww, zz), df_neg(df_add(xx, yy))), 1.f);
+    const DF r01 = ent(df_add(xy, df_neg(wz)), 2.f), r10 = ent(df_add(xy, wz), 2.f);
+    const DF r02 = ent(df_add(xz, wy), 2.f), r20 = ent(df_add(xz, df_neg(wy)), 2.f);
+    const DF r12 = ent(df_add(yz, df_neg(wx)), 2.f), r21 = ent(df_add(yz, wx), 2.f);
+    o.e1 = make_float4(r00.hi, r10.hi, r20.hi, 1.f);
+    o.e2 = make_float4(r01.hi, r11.hi, r21.hi, 0.f);
+    o.e3 = make_float4(r02.hi, r12.hi, r22.hi, 0.f);
+    // slab-kernel constants; the scaled axes are rounded once from the
+    // double-float product as well
     const float r = sqrtf(tscale);
     const float n[3] = {o.e3.x, o.e3.y, o.e3.z};
     const float a1[3] = {o.e1.x, o.e1.y, o.e1.z};
@@ -142,20 +217,42 @@ __global__ void k_prep(const float4 *__restrict__ quats, int count, float tscale
     const int d = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
     const int ia = d == 0 ? 1 : 0;
     const int ib = d == 2 ? 1 : 2;
-    o.e1s = make_float4(r * o.e1.x, r * o.e1.y, r * o.e1.z, __int_as_float(d | (ia << 8) | (ib << 16)));
-    o.e2s = make_float4(r * o.e2.x, r * o.e2.y, r * o.e2.z, 1.0f / n[d]);
-    o.e3s = make_float4(r * o.e3.x, r * o.e3.y, r * o.e3.z, n[d]);
+    // Exact geometry: each scaled component c = r e is split into a part on
+    // a grid of step gs (a power of two) and the remainder: with |v_i| <= 512
+    // every partial sum of (grid part) . v is a multiple of gs below 2^24 gs,
+    // so the slab kernel forms it exactly in FP32, and the remainder
+    // (|.| <= gs / 2) adds the rest with an error far below a table step.
+    // Otherwise the component is rounded once and the remainder is zero.
+    int ex;
+    frexpf(1.7321f * 512.f * r * 0x1p-24f * 1.001f, &ex);
+    const float gs = ldexpf(1.f, ex);
+    float g3[9], b3[9];
+    const DF cols[9] = {r00, r10, r20, r01, r11, r21, r02, r12, r22};
+    for (int k = 0; k < 9; ++k) {
+        const DF c = df_scale(cols[k], r);
+        g3[k] = exact ? rintf(c.hi / gs) * gs : c.hi;
+        b3[k] = exact ? (c.hi - g3[k]) + c.lo : 0.f;
+    }
+    o.e1s = make_float4(g3[0], g3[1], g3[2], __int_as_float(d | (ia << 8) | (ib << 16)));
+    o.e2s = make_float4(g3[3], g3[4], g3[5], 1.0f / n[d]);
+    o.e3s = make_float4(g3[6], g3[7], g3[8], n[d]);
+    if (exact) {
+        rem[3 * s] = make_float4(b3[0], b3[1], b3[2], 0.f);
+        rem[3 * s + 1] = make_float4(b3[3], b3[4], b3[5], 0.f);
+        rem[3 * s + 2] = make_float4(b3[6], b3[7], b3[8], 0.f);
+    }
     o.p1 = make_float4(a1[d], a1[ia], a1[ib], n[ia]);
     o.p2 = make_float4(a2[d], a2[ia], a2[ib], n[ib]);
     orient[s] = o;
 }
 
-hipError_t launch_prep(const float *quats, int count, float tscale, Orient *orient, Counters *ctr, unsigned *queue,
-                       hipStream_t st)
+hipError_t launch_prep(const float *quats, int count, float tscale, bool exact, Orient *orient, float4 *rem,
+                       Counters *ctr, unsigned *queue, hipStream_t st)
 {
     const int blocks = count > 0 ? (count + 255) / 256 : 1;
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st,
-                       reinterpret_cast<const float4 *>(quats), count, tscale, orient, ctr, queue);
+                       reinterpret_cast<const float4 *>(quats), count, tscale, exact ? 1 : 0, orient, rem, ctr,
+                       queue);
     return hipGetLastError();
 }
 

@@ -42,10 +42,15 @@ __device__ __forceinline__ float2 decode_sample(const unsigned char *__restrict_
 
 // Per-slice orientation record written by the prep kernel (128 bytes).
 // e1, e2 are the images of the slice's x and y axes in the volume, e3 the
-// plane normal (columns of R).  e1.w is 1 for a usable slice, 0 otherwise.
+// plane normal (columns of R), each component the correctly rounded value
+// for the given quaternion.  e1.w is 1 for a usable slice, 0 otherwise.
 // The rest are per-slice constants of the slab kernel, computed once here
 // instead of once per (tile, slice):
-//   e1s, e2s, e3s  the axes scaled by sqrt((N-1)/a^2) (table units);
+//   e1s, e2s, e3s  the axes scaled by sqrt((N-1)/a^2) (table units),
+//                  rounded to FP32; with exact geometry, their part on a
+//                  grid of a power-of-two step gs instead, with the
+//                  remainders in a separate array of three float4 per slice
+//                  (xyz: the remainders of e1s, e2s, e3s; see exact_geometry);
 //   e1s.w          the axes' order as int bits d | ia << 8 | ib << 16: d is
 //                  e3's dominant axis, ia < ib the other two;
 //   e2s.w          1 / e3[d];  e3s.w  e3[d];
@@ -56,6 +61,17 @@ struct Orient {
     float4 e1s, e2s, e3s;
     float4 p1, p2;
 };
+
+// Exact window geometry for the slab kernel.  A voxel's position in table
+// units, c . v for a scaled axis c, is formed in FP32; at |v| ~ 500 its
+// rounding (an ulp of ~27000) moves the table index by ~0.1 steps, a
+// relative weight error of ~1e-4 per sample far from the origin.  With
+// exact geometry c = g + b with g on a grid fine enough that g . v is exact
+// for |v_i| <= 512, and b . v (|b| <= gs / 2) is added after the large part
+// has cancelled, so the error drops to an ulp of the offset itself.  It costs
+// three FMAs per coordinate and hit, so it is used where coordinates are
+// large: boxes above 256.
+inline bool exact_geometry(const Geom &g) { return g.h > 128; }
 
 // Workspace counters (device, 256 bytes at the start of the workspace).
 struct Counters {
@@ -80,6 +96,7 @@ struct JobDesc {
     Geom g;
     const void *slices;      // this batch's stored slices
     const Orient *orient;    // orientation records of this batch
+    const float4 *rem;       // exact geometry: axis remainders, 3 per slice
     float4 *partials;        // partial-sum slots of split tiles
     float2 *G;
     float *W;
@@ -94,9 +111,11 @@ struct JobTable {
 // Host launchers (defined in kernels.hip).
 hipError_t launch_zero(float *p, size_t count, hipStream_t st);
 // Orientation records for a batch; adds `count` to ctr->inserted; zeroes
-// *queue (a work-queue head) when given.
-hipError_t launch_prep(const float *quats, int count, float tscale, Orient *orient, Counters *ctr, unsigned *queue,
-                       hipStream_t st);
+// *queue (a work-queue head) when given.  `exact`: split the scaled axes for
+// the slab kernel's exact geometry (the launch that reads the records must
+// be built for the same choice).
+hipError_t launch_prep(const float *quats, int count, float tscale, bool exact, Orient *orient, float4 *rem,
+                       Counters *ctr, unsigned *queue, hipStream_t st);
 hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices,
                                const Orient *orient, int count, const float2 *table,
                                int inner_chunk, int waves_per_block, float2 *G, float *W,
@@ -111,9 +130,9 @@ hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   hipStream_t st);
 // Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
 size_t slab_lds_bytes(const Geom &g, int waves_per_block);
-hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
-                              int nitems, int inner_chunk, int blocks, int waves_per_block, Counters *ctr,
-                              hipStream_t st);
+hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, bool exact, const float2 *table,
+                              const Item *items, int nitems, int inner_chunk, int blocks, int waves_per_block,
+                              Counters *ctr, hipStream_t st);
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st);
 hipError_t launch_finalize(const Geom &g, float2 *G, float *W, float2 *V, float thr,
                            hipStream_t st);

@@ -180,8 +180,10 @@ Layout layout_for(const recon_params &p, int nitems, size_t partial_vox)
     off = align_up(off + sizeof(Counters), 256);
     L.table = off;
     off = align_up(off + static_cast<size_t>(p.table_size) * sizeof(float2), 256);
+    // orientation records, then the exact-geometry axis remainders (3 float4
+    // per slice)
     L.orient = off;
-    off = align_up(off + static_cast<size_t>(p.max_batch) * sizeof(Orient), 256);
+    off = align_up(off + static_cast<size_t>(p.max_batch) * (sizeof(Orient) + 3 * sizeof(float4)), 256);
     L.items = off;
     off = align_up(off + static_cast<size_t>(nitems) * sizeof(Item), 256);
     L.partials = off;
@@ -270,6 +272,12 @@ struct recon_ctx {
     hipEvent_t ev_stop;
     TuneState tune;
 };
+
+// exact-geometry axis remainders: after the max_batch orientation records
+static float4 *orient_rem(recon_ctx *c)
+{
+    return reinterpret_cast<float4 *>(c->ws + c->L.orient + static_cast<size_t>(c->p.max_batch) * sizeof(Orient));
+}
 
 static recon_status tune_collect(recon_ctx *c);
 static recon_status tune_finish(recon_ctx *c);
@@ -463,9 +471,11 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     }
     Counters *ctr = reinterpret_cast<Counters *>(c->ws + c->L.ctr);
     Orient *orient = reinterpret_cast<Orient *>(c->ws + c->L.orient);
+    float4 *rem = orient_rem(c);
     const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
     const void *slices = d_slices;
-    hipError_t e = recon::launch_prep(d_quats, count, c->g.tscale, orient, ctr, &ctr->queue, c->stream);
+    const bool exact = recon::exact_geometry(c->g);
+    hipError_t e = recon::launch_prep(d_quats, count, c->g.tscale, exact, orient, rem, ctr, &ctr->queue, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
     if (c->ev_start) {
         e = hipEventRecord(c->ev_start, c->stream);
@@ -498,8 +508,8 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     if (slab) {
         std::memset(&jt, 0, sizeof(jt));
         jt.njobs = 1;
-        jt.job[0] = {c->g, slices, orient, partials, c->G, c->W, count, 0};
-        e = recon::launch_insert_slab(jt, c->p.table_lerp != 0, c->cfg.slab_flags & 3, table, items, nitems,
+        jt.job[0] = {c->g, slices, orient, rem, partials, c->G, c->W, count, 0};
+        e = recon::launch_insert_slab(jt, c->p.table_lerp != 0, c->cfg.slab_flags & 3, exact, table, items, nitems,
                                       c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->stream);
     } else
         e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
@@ -909,15 +919,18 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
             return fail(RECON_EINVAL, "job %d: half-precision slices need scales", j);
         recon::Geom g = c->g;
         g.scales = c->p.slice_dtype == RECON_SLICE_F16 ? sc : nullptr;
-        jt.job[j] = {g, d_slices[j], reinterpret_cast<const Orient *>(c->ws + c->L.orient),
+        jt.job[j] = {g, d_slices[j], reinterpret_cast<const Orient *>(c->ws + c->L.orient), orient_rem(c),
                      reinterpret_cast<float4 *>(c->ws + c->L.partials), c->G, c->W, counts[j], 0};
     }
     Counters *bctr = reinterpret_cast<Counters *>(b->ws);
+    // one geometry mode for the whole launch: exact if any box needs it
+    bool exact = false;
+    for (int j = 0; j < nj; ++j) exact = exact || recon::exact_geometry(b->ctxs[j]->g);
     for (int j = 0; j < nj; ++j) {
         recon_ctx *c = b->ctxs[j];
         if (counts[j] == 0 && j != 0) continue;
-        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j], c->g.tscale,
-                                          reinterpret_cast<Orient *>(c->ws + c->L.orient),
+        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j], c->g.tscale, exact,
+                                          reinterpret_cast<Orient *>(c->ws + c->L.orient), orient_rem(c),
                                           reinterpret_cast<Counters *>(c->ws + c->L.ctr),
                                           j == 0 ? &bctr->queue : nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "batch prep launch");
@@ -925,8 +938,8 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
-    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, 2, table, items, b->nitems, 32, c0->num_cu, 8,
-                                             bctr, st);
+    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, 2, exact, table, items, b->nitems, 32,
+                                             c0->num_cu, 8, bctr, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items, b->nitems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");
     return RECON_OK;

@@ -145,23 +145,32 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 // scaled by s = sqrt(table scale), so squared distances are table positions
 // directly.  RIM: the rectangle reaches the disk edge, so each candidate's
 // |k| < r_max membership gates its weight.  PRELOAD: all LDS reads of the
-// window are issued before any is consumed.
-template <int WIN, bool RIM, bool LERP, bool PRELOAD>
+// window are issued before any is consumed.  EXACT: uxs and uys are exact
+// grid-part products and uxl, uyl the remainders' products, added once the
+// large parts have cancelled (else uxl, uyl are unused).
+template <int WIN, bool RIM, bool LERP, bool PRELOAD, bool EXACT>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
-                                           const Geom &g, float uxs, float uys, float uzs, float s, float inv_s,
-                                           int kx_lo, int ky_lo, float &pr, float &pi, float &pw)
+                                           const Geom &g, float uxs, float uxl, float uys, float uyl, float uzs,
+                                           float s, float inv_s, int kx_lo, int ky_lo, float &pr, float &pi,
+                                           float &pw)
 {
     constexpr int RECT = SlabShape<WIN>::RECT;
     // largest first-cell offset that keeps the window inside the buffer
     constexpr int MAXOFF = RECT * RECT - 1 - (WIN - 1) * (RECT + 1);
     // first window column / row: ceil(u - a)
-    const float fx0 = ceilf(fmaf(uxs, inv_s, -g.a));
-    const float fy0 = ceilf(fmaf(uys, inv_s, -g.a));
+    const float fx0 = ceilf(fmaf(EXACT ? uxs + uxl : uxs, inv_s, -g.a));
+    const float fy0 = ceilf(fmaf(EXACT ? uys + uyl : uys, inv_s, -g.a));
     // the staged rectangle holds every window; the clamp only guards the buffer
     const int off = min(max(__mul24(static_cast<int>(fy0) - ky_lo, RECT) + (static_cast<int>(fx0) - kx_lo), 0), MAXOFF);
     const float2 *base = rect + off;
     float dxs[WIN], dys[WIN];
-    const float dx0 = fmaf(-s, fx0, uxs), dy0 = fmaf(-s, fy0, uys);
+    float dx0 = fmaf(-s, fx0, uxs), dy0 = fmaf(-s, fy0, uys);
+    if constexpr (EXACT) {
+        // uxs and s fx0 are exact, so the fma rounds once at the size of the
+        // offset; then the small remainder
+        dx0 += uxl;
+        dy0 += uyl;
+    }
     const float uz2 = uzs * uzs;
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {
@@ -246,7 +255,7 @@ constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 // MAXW: largest work-group (in waves) the instance is built for; it sets the
 // register budget (8 waves: 256 VGPRs, two waves per SIMD; 11 waves: 168
 // VGPRs, three waves on three of the four SIMDs).
-template <int WIN, bool LERP, int FLAGS, int MAXW>
+template <int WIN, bool LERP, int FLAGS, int MAXW, bool EXACT>
 __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
                                                      const Item *__restrict__ items, int nitems, int inner_chunk,
                                                      Counters *__restrict__ ctr)
@@ -366,6 +375,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             struct Stage {
                 float4 e1s, e2s, e3s;        // axes in table units; .w: axis order, 1/e3[d], e3[d]
                 float4 p1, p2;               // e1, e2 along (d, ia, ib); .w: e3[ia], e3[ib]
+                float4 b1, b2, b3;           // remainders of the scaled axes (exact geometry)
                 int kx_lo, ky_lo, wx, wy;    // staged rectangle: columns kx_lo.., rows ky_lo..
                 int rim;                     // int, not bool: no padding bytes in the struct copies
                 int H;                       // hits
@@ -390,6 +400,13 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 st.e3s = make_float4(o[20], o[21], o[22], o[23]);
                 st.p1 = make_float4(o[24], o[25], o[26], o[27]);
                 st.p2 = make_float4(o[28], o[29], o[30], o[31]);
+                if constexpr (EXACT) {
+                    const float __attribute__((address_space(4))) *rm =
+                        const_space(reinterpret_cast<const float *>(jt.job[job].rem)) + static_cast<long>(s) * 12;
+                    st.b1 = make_float4(rm[0], rm[1], rm[2], 0.f);
+                    st.b2 = make_float4(rm[4], rm[5], rm[6], 0.f);
+                    st.b3 = make_float4(rm[8], rm[9], rm[10], 0.f);
+                }
                 st.scale = g.scales ? const_space(g.scales)[s] : 1.0f;
             };
 
@@ -564,6 +581,8 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const int H = cur.H;
                 // slice axes in table units
                 const float4 e1s = cur.e1s, e2s = cur.e2s, e3s = cur.e3s;
+                // (remainders: read only with exact geometry)
+                const float4 b1 = cur.b1, b2 = cur.b2, b3 = cur.b3;
                 for (int r = 0; r < H; r += 64) {
                     const int hh = r + lane;
                     if (hh < H) {
@@ -574,14 +593,20 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                         const float uxs = fmaf(e1s.x, vx, fmaf(e1s.y, vy, e1s.z * vz));
                         const float uys = fmaf(e2s.x, vx, fmaf(e2s.y, vy, e2s.z * vz));
                         const float uzs = fmaf(e3s.x, vx, fmaf(e3s.y, vy, e3s.z * vz));
+                        float uxl = 0.f, uyl = 0.f, uz = uzs;
+                        if constexpr (EXACT) {
+                            uxl = fmaf(b1.x, vx, fmaf(b1.y, vy, b1.z * vz));
+                            uyl = fmaf(b2.x, vx, fmaf(b2.y, vy, b2.z * vz));
+                            uz += fmaf(b3.x, vx, fmaf(b3.y, vy, b3.z * vz));
+                        }
                         float pr, pi, pw;
                         constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
                         if (cur.rim)
-                            window_lds<WIN, true, LERP, PRE>(rect, tab, g, uxs, uys, uzs, ts_root, ts_rinv,
-                                                             cur.kx_lo, cur.ky_lo, pr, pi, pw);
+                            window_lds<WIN, true, LERP, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
+                                                                    ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         else
-                            window_lds<WIN, false, LERP, PRE>(rect, tab, g, uxs, uys, uzs, ts_root, ts_rinv,
-                                                              cur.kx_lo, cur.ky_lo, pr, pi, pw);
+                            window_lds<WIN, false, LERP, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
+                                                                     ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         // a voxel appears once per slice: single writer within the wave
                         if (FLAGS & SLAB_ATOMIC) {
                             atomicAdd(&acc_c[lid].x, pr);
@@ -670,14 +695,14 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     }
 }
 
-template <int WIN, bool LERP, int FLAGS, int MAXW = 8>
+template <int WIN, bool LERP, int FLAGS, bool EXACT, int MAXW = 8>
 hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *items, int nitems, int inner_chunk,
                          int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
     const size_t lds = (static_cast<size_t>(table_words(jt.job[0].g.N)) +
                         static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
     if (wpb > MAXW) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS, MAXW>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
+    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS, MAXW, EXACT>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
                        items, nitems, inner_chunk, ctr);
     return hipGetLastError();
 }
@@ -727,10 +752,10 @@ size_t slab_lds_bytes(const Geom &g, int waves_per_block)
             static_cast<size_t>(waves_per_block) * slab_wave_words(win)) * sizeof(float);
 }
 
-hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
-                              int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr, hipStream_t st)
+template <bool EXACT>
+static hipError_t dispatch_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
+                                int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
-    if (nitems <= 0) return hipSuccess;
     const Geom &g = jt.job[0].g;
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
     // every flag combination exists for the common window (a in [1.5, 2)) with
@@ -738,24 +763,24 @@ hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const fl
     if (win == 4 && lerp && wpb > 8) {
         // three waves per SIMD: register budget of 168, window reads interleaved
         if (flags & SLAB_ATOMIC)
-            return launch_slab_t<4, true, SLAB_ATOMIC, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr,
-                                                           st);
-        return launch_slab_t<4, true, 0, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+            return launch_slab_t<4, true, SLAB_ATOMIC, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks,
+                                                                  wpb, ctr, st);
+        return launch_slab_t<4, true, 0, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
     }
     if (win == 4 && lerp) {
         switch (flags & 3) {
-        case 0: return launch_slab_t<4, true, 0>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 1: return launch_slab_t<4, true, 1>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 2: return launch_slab_t<4, true, 2>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        default: return launch_slab_t<4, true, 3>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 0: return launch_slab_t<4, true, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 1: return launch_slab_t<4, true, 1, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 2: return launch_slab_t<4, true, 2, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        default: return launch_slab_t<4, true, 3, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
         }
     }
-#define RECON_SLAB_CASE(WV)                                                                                    \
-    case WV:                                                                                                   \
-        return lerp ? launch_slab_t<WV, true, slab_default_flags<WV>()>(jt, table, items, nitems, inner_chunk,  \
-                                                                        blocks, wpb, ctr, st)                  \
-                    : launch_slab_t<WV, false, slab_default_flags<WV>()>(jt, table, items, nitems, inner_chunk, \
-                                                                         blocks, wpb, ctr, st);
+#define RECON_SLAB_CASE(WV)                                                                                   \
+    case WV:                                                                                                  \
+        return lerp ? launch_slab_t<WV, true, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,        \
+                                                                               inner_chunk, blocks, wpb, ctr, st) \
+                    : launch_slab_t<WV, false, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,       \
+                                                                                inner_chunk, blocks, wpb, ctr, st);
     switch (win) {
         RECON_SLAB_CASE(1)
         RECON_SLAB_CASE(2)
@@ -767,6 +792,15 @@ hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, const fl
         return hipErrorInvalidValue;
     }
 #undef RECON_SLAB_CASE
+}
+
+hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, bool exact, const float2 *table,
+                              const Item *items, int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr,
+                              hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    return exact ? dispatch_slab<true>(jt, lerp, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st)
+                 : dispatch_slab<false>(jt, lerp, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
 }
 
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st)

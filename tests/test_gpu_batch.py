@@ -28,9 +28,12 @@ def make_jobs(torch, dev, recon, specs, stream):
     return jobs
 
 
-def test_batch_matches_oracle_per_reconstruction(env):
+# the second case puts a box above 256 in the launch, so every box of it is
+# inserted with the slab kernel's exact geometry
+@pytest.mark.parametrize("specs", [[(32, 70), (48, 40), (20, 90), (64, 25), (34, 0)],
+                                   [(32, 70), (272, 30), (48, 40)]], ids=["small", "with_large_box"])
+def test_batch_matches_oracle_per_reconstruction(env, specs):
     torch, dev, recon = env
-    specs = [(32, 70), (48, 40), (20, 90), (64, 25), (34, 0)]
     stream = torch.cuda.current_stream()
     jobs = make_jobs(torch, dev, recon, specs, stream)
     ctxs = [j[1].ctx for j in jobs]
