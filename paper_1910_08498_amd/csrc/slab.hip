@@ -179,6 +179,17 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         const float dy = i == 0 ? dy0 : fmaf(-s, static_cast<float>(i), dy0);
         dys[i] = fmaf(dy, dy, uz2);
     }
+    // rim gate per cell: kx^2 < r_max^2 - ky^2 (integers below 2^24: exact,
+    // so the same test as kx^2 + ky^2 < r_max^2), per column and per row
+    float kx2[WIN], rem[WIN];
+    if (RIM) {
+#pragma unroll
+        for (int i = 0; i < WIN; ++i) {
+            const float kx = fx0 + static_cast<float>(i), ky = fy0 + static_cast<float>(i);
+            kx2[i] = kx * kx;
+            rem[i] = fmaf(-ky, ky, g.r2max);
+        }
+    }
     float sr = 0.f, si = 0.f, sw = 0.f;
     auto weight = [&](float tk, float t0k, float t1k, int i, int j) {
         float w;
@@ -188,10 +199,7 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         } else {
             w = tk <= static_cast<float>(g.N - 1) ? t0k : 0.f;
         }
-        if (RIM) {
-            const float kx = fx0 + static_cast<float>(i), ky = fy0 + static_cast<float>(j);
-            w = fmaf(kx, kx, ky * ky) < g.r2max ? w : 0.f;
-        }
+        if (RIM) w = kx2[i] < rem[j] ? w : 0.f;
         return w;
     };
     if (PRELOAD) {
@@ -601,7 +609,18 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                         }
                         float pr, pi, pw;
                         constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
-                        if (cur.rim)
+                        // The rectangle reaches the disk edge: gate each window
+                        // cell by |k| < r_max only in rounds where some hit's
+                        // window can reach it.  A window's cells satisfy
+                        // |kx| <= |u_x| + a + 1 (0.1 covers the remainders of
+                        // exact geometry), likewise for y.
+                        bool rim_round = false;
+                        if (cur.rim) {
+                            const float ax = fmaf(fabsf(uxs), ts_rinv, g.a + 1.1f);
+                            const float ay = fmaf(fabsf(uys), ts_rinv, g.a + 1.1f);
+                            rim_round = __ballot(fmaf(ax, ax, ay * ay) >= g.r2max) != 0ull;
+                        }
+                        if (rim_round)
                             window_lds<WIN, true, LERP, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
                                                                     ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         else
