@@ -61,7 +61,7 @@ typedef enum recon_slice_dtype {
 typedef struct recon_params {
     int32_t n;            /* slice edge; even, 4 <= n <= 1024; volume (n+1)^3 */
     float blob_radius;    /* a, 0 < a <= 2.95 (default 1.9) */
-    float blob_alpha;     /* alpha >= 0 (default 15) */
+    float blob_alpha;     /* 0 <= alpha <= 60 (default 15); alpha = 0 needs m = 0 */
     int32_t blob_order;   /* m, 0 <= m <= 8 (default 0) */
     int32_t table_size;   /* N, 2 <= N <= 65536 (default 10000) */
     int32_t table_lerp;   /* 1: linear interpolation in the table (default), 0: truncation */

@@ -84,6 +84,8 @@ recon_status validate(const recon_params *p)
         return fail(RECON_EINVAL, "blob_alpha must be in [0, 60] (got %g)", p->blob_alpha);
     if (p->blob_order < 0 || p->blob_order > 8)
         return fail(RECON_EINVAL, "blob_order must be in [0, 8] (got %d)", p->blob_order);
+    if (p->blob_alpha == 0.0f && p->blob_order > 0)
+        return fail(RECON_EINVAL, "blob_alpha 0 needs blob_order 0 (I_m(0) = 0 cannot normalise the blob)");
     if (p->table_size < 2 || p->table_size > 65536)
         return fail(RECON_EINVAL, "table_size must be in [2, 65536] (got %d)", p->table_size);
     if (p->table_lerp != 0 && p->table_lerp != 1)

@@ -195,7 +195,10 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         float w;
         if (LERP) {
             const float f = __builtin_amdgcn_fractf(tk);
-            w = fmaxf(fmaf(f, t1k - t0k, t0k), 0.f);
+            // the table lies in [0, 1] and decreases (b(0) = 1), so the lerp
+            // never exceeds 1 and clamping to [0, 1] is the cut-off's max(., 0)
+            // in one instruction (the fma's clamp modifier)
+            w = fminf(fmaxf(fmaf(f, t1k - t0k, t0k), 0.f), 1.f);
         } else {
             w = tk <= static_cast<float>(g.N - 1) ? t0k : 0.f;
         }

@@ -50,6 +50,17 @@ def test_default_params_and_sizes(recon):
     assert recon.recon_query_sizes(p)[2] > ws
 
 
+def test_degenerate_blob_rejected(recon):
+    # alpha = 0 with order m > 0: the normaliser I_m(0) is zero
+    p = recon.recon_default_params(128)
+    p.blob_alpha, p.blob_order = 0.0, 2
+    with pytest.raises(recon.ReconError) as ei:
+        recon.recon_query_sizes(p)
+    assert ei.value.status == recon.RECON_EINVAL
+    p.blob_order = 0                            # alpha = 0, m = 0: the box profile b = 1
+    recon.recon_query_sizes(p)
+
+
 @pytest.mark.parametrize("field,value", [
     ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 3.5),
     ("blob_alpha", -1.0), ("blob_order", 9), ("table_size", 1), ("table_lerp", 2),
