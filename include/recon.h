@@ -89,12 +89,13 @@ typedef struct recon_config {
                                  reads never preloaded; the default where it exists) for
                                  blob radii in [1.5, 2) with table interpolation */
     int32_t group;            /* slices staged per LDS group (binned): 1..16 */
-    int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 */
+    int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 (default 32;
+                                 64 with the 11-wave slab default) */
     int32_t split;            /* max slice-range splits of one tile (binned, slab): 1..64
-                                 (default 16) */
+                                 (default 16; 32 with the 11-wave slab default) */
     int32_t slab_flags;       /* slab variant, 4 | bits: bit 0 LDS float atomics for the
                                  accumulators, bit 1 issue all window reads before use
-                                 (default 4 | 2) */
+                                 (default 4 | 2; 4 with the 11-wave slab default) */
     int32_t reserved[10];
 } recon_config;
 
@@ -165,7 +166,10 @@ recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
  * every reconstruction ordered by estimated cost.  recon_batch_insert only
  * enqueues kernels (no host synchronisation, no allocation, no copies), so a
  * caller may capture it in a HIP graph and replay it.  Work runs on the
- * first context's stream.
+ * first context's stream.  The launch uses the single-context default
+ * configuration of the shared blob (11 waves per work-group for the 4 x 4
+ * interpolated window, else 8), and exact window geometry for every box
+ * when any box is above 256.
  * --------------------------------------------------------------------- */
 typedef struct recon_batch recon_batch;
 

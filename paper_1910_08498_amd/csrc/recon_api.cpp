@@ -383,7 +383,7 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
         c->cfg.waves_per_block = 11;
         c->cfg.slab_flags = 4;
         c->cfg.inner_chunk = 64;
-        c->cfg.split = 64;
+        c->cfg.split = 32;
     }
     if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
         // blob table too large for the slab kernel's LDS budget
@@ -816,9 +816,23 @@ struct recon_batch {
     size_t ws_bytes;
     int nitems;
     size_t off_items;
+    int wpb, flags, inner;   // slab launch configuration of the batch
 };
 
-// Combined work plan of a batch: every context's slab plan (split 32),
+// Launch configuration of a batch (the contexts share their blob): the
+// single-context default, 11 waves with interleaved window reads where that
+// instance exists and fits, else 8 waves with preloaded reads.
+struct BatchLaunch {
+    int wpb, flags, inner, split;
+};
+static BatchLaunch batch_launch(const recon_ctx *c0)
+{
+    if (slab_wide_ok(c0->g, c0->p.table_lerp != 0, c0->max_lds)) return {11, 0, 64, 32};
+    return {8, 2, 32, 32};
+}
+
+// Combined work plan of a batch: every context's slab plan (split of the
+// batch's launch configuration),
 // tagged with its job index in the tile field's top byte, in decreasing
 // estimated cost across all jobs.
 static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vector<Item> *items)
@@ -837,8 +851,9 @@ static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vecto
     }
     struct Tmp { Item it; double cost; };
     std::vector<Tmp> all;
+    const int split = batch_launch(ctxs[0]).split;
     for (int j = 0; j < njobs; ++j) {
-        const Plan pl = make_plan(ctxs[j]->p, 32, 8);
+        const Plan pl = make_plan(ctxs[j]->p, split, 8);
         // the plan is sorted by cost already; recompute a comparable cost as
         // (slice visits) for interleaving jobs: position-weighted by max_batch
         const size_t n = pl.items.size();
@@ -879,8 +894,9 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     const size_t need = align_up(sizeof(Counters), 256) + align_up(items.size() * sizeof(Item), 256);
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return fail(RECON_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return fail(RECON_ENOMEM, "batch workspace too small: %zu given, %zu needed", ws_bytes, need);
+    const BatchLaunch bl = batch_launch(ctxs[0]);
     for (int j = 0; j < njobs; ++j)
-        if (recon::slab_lds_bytes(ctxs[j]->g, 8) > ctxs[j]->max_lds)
+        if (recon::slab_lds_bytes(ctxs[j]->g, bl.wpb) > ctxs[j]->max_lds)
             return fail(RECON_ECONFIG, "the slab kernel does not fit this device for context %d", j);
     recon_batch *b = new (std::nothrow) recon_batch();
     if (!b) return fail(RECON_ENOMEM, "host allocation failed");
@@ -889,6 +905,9 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     b->ws_bytes = ws_bytes;
     b->nitems = static_cast<int>(items.size());
     b->off_items = align_up(sizeof(Counters), 256);
+    b->wpb = bl.wpb;
+    b->flags = bl.flags;
+    b->inner = bl.inner;
     hipStream_t st0 = ctxs[0]->stream;
     hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
     if (e == hipSuccess && !items.empty())
@@ -940,8 +959,8 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
-    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, 2, exact, table, items, b->nitems, 32,
-                                             c0->num_cu, 8, bctr, st);
+    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, b->flags, exact, table, items, b->nitems,
+                                             b->inner, c0->num_cu, b->wpb, bctr, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items, b->nitems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");
     return RECON_OK;
