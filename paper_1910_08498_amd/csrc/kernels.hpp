@@ -97,7 +97,7 @@ struct JobDesc {
     const void *slices;      // this batch's stored slices
     const Orient *orient;    // orientation records of this batch
     const float4 *rem;       // exact geometry: axis remainders, 3 per slice
-    float4 *partials;        // partial-sum slots of split tiles
+    float4 *partials;        // partial-sum slots of split tiles (slab: re, im, w planes of 512 floats)
     float2 *G;
     float *W;
     int count;               // slices in this batch

@@ -708,10 +708,16 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 }
             }
         } else {
+            // partial sums of a split tile: three planes (re, im, w) of TV
+            // floats per slot, so the stores and the reduction's loads are
+            // coalesced dwords with no padding
+            float *__restrict__ pp = reinterpret_cast<float *>(partials) + static_cast<size_t>(item.slot) * 3 * TV;
 #pragma unroll
             for (int k = 0; k < TV / 64; ++k) {
                 const int lid = lane + 64 * k;
-                partials[static_cast<size_t>(item.slot) * TV + lid] = make_float4(ore[k], oim[k], ow[k], 0.f);
+                pp[lid] = ore[k];
+                pp[TV + lid] = oim[k];
+                pp[2 * TV + lid] = ow[k];
             }
         }
     }
@@ -737,7 +743,7 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
     const int job = item.tile >> 24;
     const int tile = item.tile & 0xffffff;
     const Geom g = jt.job[job].g;
-    const float4 *__restrict__ partials = jt.job[job].partials;
+    const float *__restrict__ partials = reinterpret_cast<const float *>(jt.job[job].partials);
     float2 *__restrict__ G = jt.job[job].G;
     float *__restrict__ W = jt.job[job].W;
     const int lid = threadIdx.x;
@@ -752,10 +758,10 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
     if (!(ix <= g.h && iy < g.dim && iz < g.dim)) return;
     float re = 0.f, im = 0.f, w = 0.f;
     for (int k = 0; k < item.nparts; ++k) {
-        const float4 p = partials[static_cast<size_t>(item.slot + k) * TV + lid];
-        re += p.x;
-        im += p.y;
-        w += p.z;
+        const float *__restrict__ pp = partials + static_cast<size_t>(item.slot + k) * 3 * TV;
+        re += pp[lid];
+        im += pp[TV + lid];
+        w += pp[2 * TV + lid];
     }
     const size_t vi = (static_cast<size_t>(iz) * g.dim + iy) * g.dim + (ix + g.h);
     float2 gv = G[vi];
