@@ -96,7 +96,12 @@ typedef struct recon_config {
     int32_t slab_flags;       /* slab variant, 4 | bits: bit 0 LDS float atomics for the
                                  accumulators, bit 1 issue all window reads before use
                                  (default 4 | 2; 4 with the 11-wave slab default) */
-    int32_t reserved[10];
+    int32_t cu_count;         /* work-groups of the persistent insertion kernels (slab,
+                                 binned): 0 = one per compute unit of the device; set it to
+                                 the number of CUs the context's stream may use when that
+                                 stream is restricted to a subset (a CU-masked stream).
+                                 Not a tuning knob: the tuner keeps the current value */
+    int32_t reserved[9];
 } recon_config;
 
 typedef struct recon_ctx recon_ctx;
@@ -201,12 +206,21 @@ void recon_batch_destroy(recon_batch *b);
  * are runnable on the context's device.
  * --------------------------------------------------------------------- */
 typedef struct recon_tune_opts {
-    int32_t max_steps;          /* configurations to try; 0 = the whole space */
+    int32_t max_steps;          /* configurations to try; 0 = the whole space (or the
+                                   whole candidate list) */
     int32_t reserved0;
     uint64_t seed;              /* seed of the random search order */
     double target_ns_per_slice; /* stop early once a configuration reaches this
                                    insertion-kernel time per slice (0 = never) */
-    int32_t reserved[8];
+    int32_t order_count;        /* candidates: when order is not NULL, the search tries
+                                   the tuning-space indices order[0..order_count-1] in
+                                   that order (distinct, each in [0, space size)) instead
+                                   of a random permutation of the whole space; a
+                                   predictor's ranking, for example.  Host memory, read
+                                   during recon_tune_begin only */
+    int32_t reserved1;
+    const int32_t *order;
+    int32_t reserved[4];
 } recon_tune_opts;
 
 typedef struct recon_tune_info {
@@ -224,8 +238,9 @@ typedef struct recon_tune_info {
 recon_status recon_tune_space_size(const recon_ctx *ctx, int32_t *size);
 recon_status recon_tune_space_config(const recon_ctx *ctx, int32_t index, recon_config *out);
 
-/* Starts a random search: the next recon_insert_batch calls each run one
- * untried configuration, timed with events around the insertion kernel.
+/* Starts a random search (or a search over the given candidates): the next
+ * recon_insert_batch calls each run one untried configuration, timed with
+ * events around the insertion kernel.
  * Measuring a step waits for the previous step's kernel (tuning steps are
  * not overlapped, as in the paper's tuning phase).  After max_steps steps, or
  * when the target is met, the fastest configuration is selected and kept. */

@@ -504,7 +504,7 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     const Item *items = reinterpret_cast<const Item *>(c->ws + c->L.items);
     float4 *partials = reinterpret_cast<float4 *>(c->ws + c->L.partials);
     const int nitems = static_cast<int>(c->plan.items.size());
-    const int blocks = c->num_cu;
+    const int blocks = c->cfg.cu_count > 0 ? c->cfg.cu_count : c->num_cu;
     const bool slab = c->cfg.variant == RECON_VARIANT_SLAB;
     recon::JobTable jt;
     if (slab) {
@@ -582,6 +582,8 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, wpb) > c->max_lds)
         return fail(RECON_ECONFIG, "slab kernel needs %zu bytes of LDS with %d waves (device: %zu)",
                     recon::slab_lds_bytes(c->g, wpb), wpb, c->max_lds);
+    if (n.cu_count < 0 || n.cu_count > c->num_cu)
+        return fail(RECON_ECONFIG, "cu_count must be in [0, %d] (got %d)", c->num_cu, n.cu_count);
     *out = n;
     return RECON_OK;
 }
@@ -623,6 +625,7 @@ static std::vector<recon_config> tuning_space(const recon_ctx *c)
                         in.inner_chunk = inner;
                         in.split = sp;
                         in.slab_flags = fl;
+                        in.cu_count = c->cfg.cu_count;   // a property of the stream, not tuned
                         recon_config r;
                         const std::string keep = g_err;
                         if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
@@ -710,18 +713,36 @@ recon_status recon_tune_begin(recon_ctx *c, const recon_tune_opts *opts)
         if (e == hipSuccess) e = hipEventCreate(&t.ev1);
         if (e != hipSuccess) return hip_fail(e, "create tuning events");
     }
-    t.space = tuning_space(c);
-    if (t.space.empty()) return fail(RECON_ECONFIG, "empty tuning space on this device");
-    const int n = static_cast<int>(t.space.size());
-    t.order.resize(n);
-    for (int i = 0; i < n; ++i) t.order[i] = i;
-    uint64_t x = opts->seed;
-    for (int i = n - 1; i > 0; --i) {
-        const int j = static_cast<int>(splitmix64(x) % static_cast<uint64_t>(i + 1));
-        std::swap(t.order[i], t.order[j]);
+    std::vector<recon_config> space = tuning_space(c);
+    if (space.empty()) return fail(RECON_ECONFIG, "empty tuning space on this device");
+    const int n = static_cast<int>(space.size());
+    std::vector<int> order;
+    if (opts->order) {
+        // caller's candidates, in the caller's order
+        if (opts->order_count < 1 || opts->order_count > n)
+            return fail(RECON_EINVAL, "order_count must be in [1, %d] (got %d)", n, opts->order_count);
+        std::vector<char> seen(n, 0);
+        for (int i = 0; i < opts->order_count; ++i) {
+            const int k = opts->order[i];
+            if (k < 0 || k >= n) return fail(RECON_EINVAL, "order[%d] = %d outside [0, %d)", i, k, n);
+            if (seen[k]) return fail(RECON_EINVAL, "order[%d] = %d repeats a candidate", i, k);
+            seen[k] = 1;
+            order.push_back(k);
+        }
+    } else {
+        order.resize(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        uint64_t x = opts->seed;
+        for (int i = n - 1; i > 0; --i) {
+            const int j = static_cast<int>(splitmix64(x) % static_cast<uint64_t>(i + 1));
+            std::swap(order[i], order[j]);
+        }
     }
+    const int m = static_cast<int>(order.size());
+    t.space = std::move(space);
+    t.order = std::move(order);
     t.next = 0;
-    t.max_steps = opts->max_steps == 0 ? n : std::min(opts->max_steps, n);
+    t.max_steps = opts->max_steps == 0 ? m : std::min(opts->max_steps, m);
     t.target = opts->target_ns_per_slice;
     t.steps_done = 0;
     t.pending = -1;
@@ -960,7 +981,8 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
     hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, b->flags, exact, table, items, b->nitems,
-                                             b->inner, c0->num_cu, b->wpb, bctr, st);
+                                             b->inner, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
+                                             b->wpb, bctr, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items, b->nitems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");
     return RECON_OK;

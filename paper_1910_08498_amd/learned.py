@@ -8,8 +8,18 @@ every configuration of the tuning space on each of them, turns timings into
 target distributions, and measures the regret of the predicted configuration
 against the fastest measured one (exhaustive search).
 
-Features of a workload: log2(n), log2(slices), blob radius a.  (The device is
-fixed, so its compute-unit count is not a feature here.)
+Features of a workload: log2(n), log2(slices), blob radius a, and the
+fraction of the device's compute units the reconstruction may use.  The
+last one is varied on the one device available by running the timings on a
+CU-masked stream (hipExtStreamCreateWithCUMask) with the library's cu_count
+set to match.
+
+The predictor ranks the configurations; at run time the library's tuner
+then measures its top candidates on real work (recon_tune_begin with a
+candidate order) and keeps the fastest, which also measures how far the
+top-1 prediction was from the best candidate.  When the predictor is not
+confident (top probability below a threshold) the tuner falls back to its
+random search.
 
 Configurations are identified by their knob values (variant, waves per
 work-group, inner chunk, split, slab flags).  The runnable set depends on the
@@ -19,6 +29,7 @@ runnable ones are chosen for a workload.
 """
 from __future__ import annotations
 
+import ctypes
 import math
 from dataclasses import dataclass, field
 
@@ -28,6 +39,7 @@ import torch
 from . import recon
 
 N_HIDDEN = 64
+CU_CHOICES = (64, 128, 192, 256)
 
 
 def config_key(c) -> tuple:
@@ -43,9 +55,12 @@ class TuneRecord:
     keys: list = field(default_factory=list)     # [C] configuration keys, aligned with ns_per_slice
     default_key: tuple | None = None    # the library's default configuration for this workload
     meta: dict = field(default_factory=dict)
+    cus: int = 256                      # compute units the insertion may use
+    cus_total: int = 256                # compute units of the device
 
     def features(self) -> np.ndarray:
-        return np.array([math.log2(self.n), math.log2(self.slices), self.a], dtype=np.float64)
+        return np.array([math.log2(self.n), math.log2(self.slices), self.a, self.cus / self.cus_total],
+                        dtype=np.float64)
 
 
 def union_keys(records) -> list:
@@ -70,24 +85,78 @@ def time_matrix(records, keys) -> np.ndarray:
     return ns
 
 
-def sample_workloads(seed: int, count: int, n_range=(48, 384), s_range=(1000, 50000), a_range=(1.5, 2.5)):
-    """Seeded workload parameters: n even (uniform), slices log-uniform, a uniform."""
+def sample_workloads(seed: int, count: int, n_range=(48, 384), s_range=(1000, 50000), a_range=(1.5, 2.5),
+                     cu_choices=CU_CHOICES):
+    """Seeded workload parameters (n, slices, a, CUs): n even (uniform), slices
+    log-uniform, a uniform, CUs uniform over cu_choices."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
         n = int(rng.integers(n_range[0] // 2, n_range[1] // 2 + 1)) * 2
         s = int(round(math.exp(rng.uniform(math.log(s_range[0]), math.log(s_range[1])))))
         a = float(rng.uniform(*a_range))
-        out.append((n, s, a))
+        cus = int(cu_choices[int(rng.integers(0, len(cu_choices)))])
+        out.append((n, s, a, cus))
     return out
 
 
+def cu_mask_words(cus: int, total: int, groups: int = 8) -> list:
+    """CU mask (32 bits per word) selecting `cus` of `total` compute units
+    spread evenly: the first cus/groups units of each of `groups` equal
+    blocks of the CU numbering.  Whether the numbering runs block by block
+    over the XCDs or round-robin across them, every XCD gets the same share."""
+    if total % groups or cus % groups or not 0 < cus <= total:
+        raise ValueError(f"cus ({cus}) and total ({total}) must be positive multiples of {groups}, cus <= total")
+    per, take = total // groups, cus // groups
+    words = [0] * ((total + 31) // 32)
+    for g in range(groups):
+        for j in range(take):
+            b = g * per + j
+            words[b // 32] |= 1 << (b % 32)
+    return words
+
+
+class CUMaskedStream:
+    """A HIP stream restricted to `cus` compute units (default priority), as a
+    torch external stream; destroyed on close()."""
+
+    def __init__(self, cus: int, device="cuda:0"):
+        self.dev = torch.device(device)
+        total = torch.cuda.get_device_properties(self.dev).multi_processor_count
+        words = cu_mask_words(cus, total)
+        hip = ctypes.CDLL("libamdhip64.so")
+        self._destroy = hip.hipStreamDestroy
+        self._destroy.argtypes = [ctypes.c_void_p]
+        create = hip.hipExtStreamCreateWithCUMask
+        create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        handle = ctypes.c_void_p()
+        arr = (ctypes.c_uint32 * len(words))(*words)
+        with torch.cuda.device(self.dev):
+            rc = create(ctypes.byref(handle), len(words), arr)
+        if rc != 0:
+            raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({rc})")
+        self.handle = handle.value
+        self.stream = torch.cuda.ExternalStream(self.handle, device=self.dev)
+        self.cus, self.total = cus, total
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize(self.dev)
+            self._destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+
 def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, device="cuda:0",
-               repeats: int = 1) -> TuneRecord:
+               repeats: int = 1, cus: int | None = None) -> TuneRecord:
     """Times every configuration of the tuning space on one batch of
     min(slices, batch_cap) synthetic slices (random complex samples, uniform
-    orientations: the cost depends on the geometry, not the values)."""
+    orientations: the cost depends on the geometry, not the values).  With
+    `cus` below the device's CU count the insertion runs on a CU-masked
+    stream with the library's cu_count set to match."""
     dev = torch.device(device)
+    total = torch.cuda.get_device_properties(dev).multi_processor_count
+    cus = total if cus is None else int(cus)
+    masked = CUMaskedStream(cus, dev) if cus < total else None
     count = min(slices, batch_cap)
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
@@ -95,7 +164,11 @@ def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, 
     sl = torch.randn((count, n, h + 1, 2), generator=g, device=dev, dtype=torch.float32)
     sl = torch.view_as_complex(sl).contiguous()
     q = torch.randn((count, 4), generator=g, device=dev, dtype=torch.float32)
-    rec = recon.Reconstruction(n, device=dev, max_batch=count, blob_radius=float(np.float32(a)))
+    torch.cuda.synchronize(dev)
+    rec = recon.Reconstruction(n, device=dev, max_batch=count, blob_radius=float(np.float32(a)),
+                               stream=masked.stream if masked else None)
+    if masked:
+        rec.set_config(cu_count=cus)
     default_key = config_key(recon.recon_get_config(rec.ctx))
     size = recon.recon_tune_space_size(rec.ctx)
     ns = np.zeros(size)
@@ -117,7 +190,10 @@ def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, 
             best = min(best, e0.elapsed_time(e1))
         ns[i] = best * 1e6 / count
     rec.close()
-    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns, keys=keys, default_key=default_key)
+    if masked:
+        masked.close()
+    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns, keys=keys, default_key=default_key, cus=cus,
+                      cus_total=total)
 
 
 def soft_targets(ns: np.ndarray, temperature: float = 0.02) -> np.ndarray:
@@ -141,9 +217,9 @@ class Normalizer:
 class Predictor:
     """MLP features -> configuration scores, trained with the library's kernels."""
 
-    def __init__(self, n_out: int, seed: int = 0, device="cuda:0"):
+    def __init__(self, n_out: int, seed: int = 0, device="cuda:0", n_in: int = 4):
         self.dev = torch.device(device)
-        self.n_in, self.H, self.C = 3, N_HIDDEN, n_out
+        self.n_in, self.H, self.C = n_in, N_HIDDEN, n_out
         rng = np.random.default_rng(seed)
         shapes = [(self.n_in, self.H), (self.H,), (self.H, self.H), (self.H,), (self.H, self.C), (self.C,)]
         parts = []
@@ -197,6 +273,73 @@ def random_search_regret(ns: np.ndarray, steps: int, trials: int = 200, seed: in
     return out / trials
 
 
+def ranked_candidates(prob: np.ndarray, runnable: np.ndarray, k: int) -> np.ndarray:
+    """Indices of the k most probable runnable configurations, best first."""
+    p = np.where(runnable, prob, -np.inf)
+    order = np.argsort(-p, kind="stable")
+    return order[:min(k, int(runnable.sum()))]
+
+
+def guided_regret(ns: np.ndarray, prob: np.ndarray, k: int) -> np.ndarray:
+    """Regret of measuring the predictor's top-k runnable configurations and
+    keeping the fastest (k tuning steps)."""
+    out = np.zeros(ns.shape[0])
+    for w in range(ns.shape[0]):
+        ok = np.isfinite(ns[w])
+        cand = ranked_candidates(prob[w], ok, k)
+        out[w] = ns[w, cand].min() / ns[w, ok].min() - 1.0
+    return out
+
+
+def policy_regret(ns: np.ndarray, prob: np.ndarray, k: int, tau: float, budget: int, trials: int = 200,
+                  seed: int = 0):
+    """The run-time policy: if the top probability is at least tau, measure
+    the top-k predicted configurations; otherwise fall back to a random search
+    of `budget` steps.  Returns (regret per workload, steps per workload,
+    fallback mask)."""
+    conf = np.where(np.isfinite(ns), prob, -np.inf).max(axis=1)
+    fallback = conf < tau
+    reg = guided_regret(ns, prob, k)
+    if fallback.any():
+        reg[fallback] = random_search_regret(ns[fallback], budget, trials=trials, seed=seed)
+    steps = np.where(fallback, budget, k)
+    return reg, steps, fallback
+
+
+def tune_with_predictor(rec, model, keys: list, features: np.ndarray, k: int = 3, tau: float = 0.2,
+                        budget: int = 10, seed: int = 0) -> dict:
+    """Starts the library's tuner on a live reconstruction: the predictor's
+    top-k runnable configurations in rank order when it is confident, else a
+    random search of `budget` steps.  The caller then performs its
+    recon_insert_batch calls (each tuning step is real work); `judge` reads
+    the outcome afterwards."""
+    size = recon.recon_tune_space_size(rec.ctx)
+    space_keys = [config_key(recon.recon_tune_space_config(rec.ctx, i)) for i in range(size)]
+    col = {kk: i for i, kk in enumerate(keys)}
+    prob = model.predict(features.reshape(1, -1))[0]
+    runnable = np.array([kk in col for kk in space_keys])
+    p_space = np.array([prob[col[kk]] if kk in col else -np.inf for kk in space_keys])
+    conf = float(p_space[runnable].max()) if runnable.any() else 0.0
+    if conf >= tau:
+        order = [int(i) for i in ranked_candidates(p_space, runnable, k)]
+        recon.recon_tune_begin(rec.ctx, order=order)
+        return {"policy": "predicted", "order": order, "confidence": conf}
+    recon.recon_tune_begin(rec.ctx, max_steps=budget, seed=seed)
+    return {"policy": "random_search", "order": None, "confidence": conf}
+
+
+def judge(rec, plan: dict) -> dict:
+    """Outcome of a tuning run started by tune_with_predictor: the selected
+    configuration and, for a predicted order, the measured regret of the
+    top-1 prediction against the fastest measured candidate."""
+    info = recon.recon_tune_get_info(rec.ctx)
+    out = dict(plan, steps=int(info.steps_done), best_index=int(info.best_index),
+               best_ns_per_slice=float(info.best_ns_per_slice), active=bool(info.active))
+    if plan["order"] and info.steps_done >= 1:
+        out["top1_is_best"] = plan["order"][0] == info.best_index
+    return out
+
+
 def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temperature: float = 0.02,
              seed: int = 0, search_budget: int = 10) -> dict:
     """Trains on `train` records and reports regrets on `test` records."""
@@ -205,9 +348,10 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
     Ytr = soft_targets(time_matrix(train, keys), temperature)
     Xte = np.stack([r.features() for r in test])
     NSte = time_matrix(test, keys)
-    model = Predictor(Ytr.shape[1], seed=seed)
+    model = Predictor(Ytr.shape[1], seed=seed, n_in=Xtr.shape[1])
     losses = model.fit(Xtr, Ytr, steps=steps, lr=lr)
-    scores = np.where(np.isfinite(NSte), model.predict(Xte), -np.inf)    # only runnable choices
+    prob = model.predict(Xte)
+    scores = np.where(np.isfinite(NSte), prob, -np.inf)    # only runnable choices
     pred = scores.argmax(axis=1)
     fin = np.where(np.isfinite(NSte), NSte, np.nan)
     out = {
@@ -218,7 +362,13 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
         "regret_random_search_mean": float(random_search_regret(NSte, search_budget, seed=seed).mean()),
         "random_search_budget": search_budget,
         "mean_config_over_best": float((np.nanmean(fin, axis=1) / NSte.min(axis=1)).mean()),
+        "regret_top3_mean": float(guided_regret(NSte, prob, 3).mean()),
+        "regret_random_search3_mean": float(random_search_regret(NSte, 3, seed=seed).mean()),
     }
+    reg, st, fb = policy_regret(NSte, prob, 3, 0.2, search_budget, seed=seed)
+    out["policy"] = {"k": 3, "tau": 0.2, "fallback_budget": search_budget, "regret_mean": float(reg.mean()),
+                     "regret_max": float(reg.max()), "steps_mean": float(st.mean()),
+                     "fallback_fraction": float(fb.mean())}
     col = {k: i for i, k in enumerate(keys)}
     if all(r.default_key in col and np.isfinite(NSte[w, col[r.default_key]]) for w, r in enumerate(test)):
         d = np.array([col[r.default_key] for r in test])
@@ -243,9 +393,9 @@ def main(argv=None):
     records = []
     params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
         sample_workloads(2000, args.test, n_range=(48, args.n_max))
-    for k, (n, s, a) in enumerate(params):
-        records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap))
-        print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} "
+    for k, (n, s, a, cus) in enumerate(params):
+        records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap, cus=cus))
+        print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} CUs={cus} "
               f"best {records[-1].ns_per_slice.min():.1f} ns/slice ({time.time() - t0:.0f} s)",
               file=sys.stderr, flush=True)
     res = evaluate(records[:args.train], records[args.train:], steps=args.steps)

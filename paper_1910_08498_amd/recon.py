@@ -30,12 +30,14 @@ class recon_params(ctypes.Structure):
 class recon_config(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("inner_chunk", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("slab_flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 10)]
+                ("slab_flags", ctypes.c_int32), ("cu_count", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
 
 
 class recon_tune_opts(ctypes.Structure):
     _fields_ = [("max_steps", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("target_ns_per_slice", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+                ("target_ns_per_slice", ctypes.c_double), ("order_count", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("order", ctypes.POINTER(ctypes.c_int32)),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class recon_tune_info(ctypes.Structure):
@@ -184,9 +186,15 @@ def recon_tune_space_config(ctx, index: int) -> recon_config:
     return c
 
 
-def recon_tune_begin(ctx, max_steps: int = 0, seed: int = 0, target_ns_per_slice: float = 0.0):
+def recon_tune_begin(ctx, max_steps: int = 0, seed: int = 0, target_ns_per_slice: float = 0.0, order=None):
+    """order: optional sequence of tuning-space indices to try in that order."""
     o = recon_tune_opts()
     o.max_steps, o.seed, o.target_ns_per_slice = int(max_steps), int(seed), float(target_ns_per_slice)
+    keep = None
+    if order is not None:
+        keep = (ctypes.c_int32 * len(order))(*[int(k) for k in order])
+        o.order_count = len(order)
+        o.order = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
     _check(load_library().recon_tune_begin(ctx, ctypes.byref(o)))
 
 

@@ -97,3 +97,28 @@ def test_init_rejects_small_workspace_without_touching_device(recon):
 
 def test_version(recon):
     assert "gfx950" in recon.recon_version()
+
+
+def test_struct_layouts_match_the_header(recon, tmp_path):
+    # sizes and offsets from a C program built against include/recon.h
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "recon.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(recon_params), sizeof(recon_config),
+           offsetof(recon_config, cu_count), sizeof(recon_tune_opts), offsetof(recon_tune_opts, order_count),
+           offsetof(recon_tune_opts, order), sizeof(recon_tune_info));
+    return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(recon.recon_params), ctypes.sizeof(recon.recon_config), recon.recon_config.cu_count.offset,
+            ctypes.sizeof(recon.recon_tune_opts), recon.recon_tune_opts.order_count.offset,
+            recon.recon_tune_opts.order.offset, ctypes.sizeof(recon.recon_tune_info)]
+    assert got == want

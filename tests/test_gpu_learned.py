@@ -22,9 +22,9 @@ def test_learned_predictor_end_to_end(env):
     train_p = learned.sample_workloads(11, 14, n_range=(48, 112), s_range=(200, 2000))
     test_p = learned.sample_workloads(12, 6, n_range=(48, 112), s_range=(200, 2000))
     recs = []
-    for k, (n, s, a) in enumerate(train_p + test_p):
-        print(f"[gpu] learned timing workload {k} n={n} S={s} a={a:.2f}", flush=True)
-        recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=1))
+    for k, (n, s, a, cus) in enumerate(train_p + test_p):
+        print(f"[gpu] learned timing workload {k} n={n} S={s} a={a:.2f} CUs={cus}", flush=True)
+        recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=1, cus=cus))
     for r in recs:
         assert len(r.keys) == r.ns_per_slice.size and np.all(r.ns_per_slice > 0)
         assert r.default_key in r.keys                 # the default is a member of the space
@@ -40,3 +40,30 @@ def test_learned_predictor_end_to_end(env):
     # tens of microseconds it is within timing noise)
     assert np.isfinite(res["regret_learned_mean"]) and res["regret_learned_mean"] >= 0.0
     assert res["regret_learned_mean"] < 0.5 * (res["mean_config_over_best"] - 1.0)
+    assert res["regret_top3_mean"] <= res["regret_learned_mean"] + 1e-12     # top-3 contains top-1
+    assert 0.0 <= res["policy"]["fallback_fraction"] <= 1.0
+
+    # live: the tuner measures the predictor's candidates on real insertions
+    keys_u = learned.union_keys(recs[:14])
+    Xtr = np.stack([r.features() for r in recs[:14]])
+    model = learned.Predictor(len(keys_u), n_in=Xtr.shape[1])
+    model.fit(Xtr, learned.soft_targets(learned.time_matrix(recs[:14], keys_u)), steps=300)
+    r = recs[14]
+    rec = recon.Reconstruction(r.n, device=torch.device("cuda:0"), max_batch=200,
+                               blob_radius=float(np.float32(r.a)))
+    plan = learned.tune_with_predictor(rec, model, keys_u, r.features(), k=3, tau=0.0)
+    assert plan["policy"] == "predicted" and len(plan["order"]) == 3
+    sl = torch.zeros((200, r.n, r.n // 2 + 1), dtype=torch.complex64, device="cuda:0")
+    q = torch.tensor([[1.0, 0.0, 0.0, 0.0]] * 200, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        recon.recon_insert_batch(rec.ctx, sl, None, q, 200)
+    recon.recon_tune_end(rec.ctx)
+    out = learned.judge(rec, plan)
+    print("   live:", out, flush=True)
+    assert out["steps"] == 3 and out["best_index"] in plan["order"] and not out["active"]
+    rec.close()
+    rec = recon.Reconstruction(r.n, device=torch.device("cuda:0"), blob_radius=float(np.float32(r.a)))
+    plan = learned.tune_with_predictor(rec, model, keys_u, r.features(), tau=1.1)   # never confident
+    assert plan["policy"] == "random_search"
+    recon.recon_tune_end(rec.ctx)
+    rec.close()

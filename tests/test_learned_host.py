@@ -40,3 +40,34 @@ def test_regret_and_random_search_use_runnable_configs_only():
     # one random pick: mean over the three runnable configurations of t / t_best - 1
     r1 = learned.random_search_regret(ns, steps=1, trials=3000, seed=1)[0]
     assert r1 == pytest.approx((1.0 + 0.0 + 3.0) / 3, abs=0.1)
+
+
+def test_cu_mask_spreads_over_blocks_of_the_numbering():
+    w = learned.cu_mask_words(64, 256)
+    assert len(w) == 8 and sum(bin(x).count("1") for x in w) == 64
+    bits = [b for b in range(256) if w[b // 32] >> (b % 32) & 1]
+    # 8 per block of 32 (block-major numbering) and 8 per residue mod 8 (round-robin numbering)
+    assert np.bincount(np.array(bits) // 32, minlength=8).tolist() == [8] * 8
+    assert np.bincount(np.array(bits) % 8, minlength=8).tolist() == [8] * 8
+    assert sum(bin(x).count("1") for x in learned.cu_mask_words(256, 256)) == 256
+    with pytest.raises(ValueError):
+        learned.cu_mask_words(60, 256)
+
+
+def test_guided_search_and_fallback_policy():
+    ns = np.array([[4.0, 1.0, 2.0, np.inf],
+                   [1.0, 3.0, 2.0, 5.0]])
+    prob = np.array([[0.1, 0.2, 0.6, 0.1],       # ranks config 2 first, config 1 second
+                     [0.05, 0.5, 0.05, 0.4]])    # ranks config 1, then 3: never the best
+    assert learned.ranked_candidates(prob[0], np.isfinite(ns[0]), 2).tolist() == [2, 1]
+    assert learned.ranked_candidates(prob[0], np.isfinite(ns[0]), 9).tolist() == [2, 1, 0]  # runnable only
+    g1 = learned.guided_regret(ns, prob, 1)
+    g2 = learned.guided_regret(ns, prob, 2)
+    assert g1.tolist() == [1.0, 2.0]             # top-1: 2/1 - 1 and 3/1 - 1
+    assert g2.tolist() == [0.0, 2.0]             # the second candidate of workload 0 is its best
+    assert np.all(learned.guided_regret(ns, prob, 4) == 0.0)
+    # confident on workload 0 only (tau = 0.55): workload 1 falls back to a full random search
+    reg, steps, fb = learned.policy_regret(ns, prob, 2, 0.55, budget=4, trials=20)
+    assert fb.tolist() == [False, True]
+    assert steps.tolist() == [2, 4]
+    assert reg.tolist() == [0.0, 0.0]
