@@ -306,7 +306,7 @@ def policy_regret(ns: np.ndarray, prob: np.ndarray, k: int, tau: float, budget: 
     return reg, steps, fallback
 
 
-def tune_with_predictor(rec, model, keys: list, features: np.ndarray, k: int = 3, tau: float = 0.2,
+def tune_with_predictor(rec, model, keys: list, features: np.ndarray, k: int = 3, tau: float = 0.05,
                         budget: int = 10, seed: int = 0) -> dict:
     """Starts the library's tuner on a live reconstruction: the predictor's
     top-k runnable configurations in rank order when it is confident, else a
@@ -365,14 +365,34 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
         "regret_top3_mean": float(guided_regret(NSte, prob, 3).mean()),
         "regret_random_search3_mean": float(random_search_regret(NSte, 3, seed=seed).mean()),
     }
-    reg, st, fb = policy_regret(NSte, prob, 3, 0.2, search_budget, seed=seed)
-    out["policy"] = {"k": 3, "tau": 0.2, "fallback_budget": search_budget, "regret_mean": float(reg.mean()),
-                     "regret_max": float(reg.max()), "steps_mean": float(st.mean()),
-                     "fallback_fraction": float(fb.mean())}
+    conf = np.where(np.isfinite(NSte), prob, -np.inf).max(axis=1)
+    out["confidence_quartiles"] = [float(x) for x in np.quantile(conf, [0.25, 0.5, 0.75])]
+    out["policy"] = []
+    for tau in (0.02, 0.05, 0.1, 0.2):
+        reg, st, fb = policy_regret(NSte, prob, 3, tau, search_budget, seed=seed)
+        out["policy"].append({"k": 3, "tau": tau, "fallback_budget": search_budget,
+                              "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
+                              "steps_mean": float(st.mean()), "fallback_fraction": float(fb.mean())})
     col = {k: i for i, k in enumerate(keys)}
     if all(r.default_key in col and np.isfinite(NSte[w, col[r.default_key]]) for w, r in enumerate(test)):
         d = np.array([col[r.default_key] for r in test])
         out["regret_default_mean"] = float(regret(NSte, d).mean())
+    return out
+
+
+def portability_matrix(records) -> np.ndarray:
+    """Performance portability of tuned configurations: entry [x, y] is the
+    fastest time on workload y over the time, on y, of the configuration
+    tuned (fastest) on workload x (1 on the diagonal; nan where x's best does
+    not run on y)."""
+    keys = union_keys(records)
+    ns = time_matrix(records, keys)
+    best = ns.argmin(axis=1)
+    out = np.empty((len(records), len(records)))
+    for x in range(len(records)):
+        for y in range(len(records)):
+            t = ns[y, best[x]]
+            out[x, y] = ns[y].min() / t if np.isfinite(t) else np.nan
     return out
 
 
@@ -388,8 +408,23 @@ def main(argv=None):
     ap.add_argument("--n-max", type=int, default=384)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--portability", action="store_true",
+                    help="instead: tune at one box size (or CU count), run at another")
     args = ap.parse_args(argv)
     t0 = time.time()
+    if args.portability:
+        res = {}
+        boxes = (32, 50, 64, 90, 128)
+        recs = [time_space(n, 1500, 1.9, seed=n, batch_cap=1500) for n in boxes]
+        res["boxes"] = {"labels": list(boxes), "slices": 1500, "a": 1.9,
+                        "matrix": np.round(portability_matrix(recs), 4).tolist()}
+        cus = CU_CHOICES
+        recs = [time_space(128, 1500, 1.9, seed=7, batch_cap=1500, cus=c) for c in cus]
+        res["cus"] = {"labels": list(cus), "n": 128, "slices": 1500, "a": 1.9,
+                      "matrix": np.round(portability_matrix(recs), 4).tolist()}
+        res["collection_s"] = time.time() - t0
+        print(json.dumps(res), flush=True)
+        return 0
     records = []
     params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
         sample_workloads(2000, args.test, n_range=(48, args.n_max))
@@ -404,8 +439,10 @@ def main(argv=None):
     print(json.dumps(res), flush=True)
     if args.out:
         keys = union_keys(records)
+        col = {k: i for i, k in enumerate(keys)}
         np.savez(args.out, features=np.stack([r.features() for r in records]),
-                 ns=time_matrix(records, keys), keys=np.array(keys), n_train=args.train)
+                 ns=time_matrix(records, keys), keys=np.array(keys), n_train=args.train,
+                 default_index=np.array([col.get(r.default_key, -1) for r in records]))
     return 0
 
 

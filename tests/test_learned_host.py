@@ -71,3 +71,14 @@ def test_guided_search_and_fallback_policy():
     assert fb.tolist() == [False, True]
     assert steps.tolist() == [2, 4]
     assert reg.tolist() == [0.0, 0.0]
+
+
+def test_portability_matrix():
+    a = rec([(1, 1, 1, 1, 1), (2, 2, 2, 2, 2)], [1.0, 2.0])      # config 0 fastest
+    b = rec([(1, 1, 1, 1, 1), (2, 2, 2, 2, 2)], [4.0, 2.0])      # config 1 fastest
+    c = rec([(2, 2, 2, 2, 2)], [3.0])                            # config 0 does not run
+    m = learned.portability_matrix([a, b, c])
+    assert m[0, 0] == 1.0 and m[1, 1] == 1.0 and m[2, 2] == 1.0
+    assert m[0, 1] == 0.5                 # a's best on b: 2 / 4
+    assert m[1, 0] == 0.5                 # b's best on a: 1 / 2
+    assert np.isnan(m[0, 2]) and m[1, 2] == 1.0
