@@ -137,7 +137,13 @@ recon_status recon_reset(recon_ctx *ctx);
  * 0 <= count <= max_batch; count = 0 is a no-op.  A quaternion that is zero
  * or not finite makes its slice contribute nothing; such slices are counted
  * (recon_stats).  Only the half box x >= 0 of G and W is accumulated here;
- * recon_finalize completes the x < 0 half from Hermitian symmetry. */
+ * recon_finalize completes the x < 0 half from Hermitian symmetry.
+ * Arithmetic: weights and accumulation in FP32; each slice's rotation is
+ * formed in double-float arithmetic and rounded once to FP32, and for n > 256
+ * the slab kernel forms window offsets exactly (a grid part of each scaled
+ * axis whose products with voxel coordinates are exact, plus a remainder),
+ * so the FP32 position error does not grow with the distance from the
+ * origin. */
 recon_status recon_insert_batch(recon_ctx *ctx, const void *d_slices, const float *d_scales,
                                 const float *d_quats, int32_t count);
 
