@@ -105,6 +105,7 @@ recon_status validate(const recon_params *p)
 // ---------------------------------------------------------------------------
 struct Plan {
     std::vector<Item> items;
+    std::vector<Item> ritems;   // split tiles (uploaded after the items)
     int nslots = 0;
 };
 
@@ -186,8 +187,10 @@ Layout layout_for(const recon_params &p, int nitems, size_t partial_vox)
     // per slice)
     L.orient = off;
     off = align_up(off + static_cast<size_t>(p.max_batch) * (sizeof(Orient) + 3 * sizeof(float4)), 256);
+    // work items, then (slab) the list of split tiles for the partial-sum
+    // reduction: at most as many entries as items
     L.items = off;
-    off = align_up(off + static_cast<size_t>(nitems) * sizeof(Item), 256);
+    off = align_up(off + 2 * static_cast<size_t>(nitems) * sizeof(Item), 256);
     L.partials = off;
     off = align_up(off + partial_vox * sizeof(float4), 256);
     L.total = off;
@@ -318,11 +321,25 @@ recon_status recon_query_sizes(const recon_params *p, size_t *g_bytes, size_t *w
     return RECON_OK;
 }
 
+// The split tiles of a work plan (their first part's item), for the
+// reduction of their partial sums.
+static std::vector<Item> split_tiles(const std::vector<Item> &items)
+{
+    std::vector<Item> r;
+    for (const Item &it : items)
+        if (it.nparts > 1 && it.part == 0) r.push_back(it);
+    return r;
+}
+
 static recon_status upload_plan(recon_ctx *c)
 {
+    c->plan.ritems = split_tiles(c->plan.items);
     if (c->plan.items.empty()) return RECON_OK;
-    hipError_t e = hipMemcpyAsync(c->ws + c->L.items, c->plan.items.data(),
-                                  c->plan.items.size() * sizeof(Item), hipMemcpyHostToDevice, c->stream);
+    // items, then the split tiles right after them
+    std::vector<Item> all(c->plan.items);
+    all.insert(all.end(), c->plan.ritems.begin(), c->plan.ritems.end());
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.items, all.data(), all.size() * sizeof(Item),
+                                  hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "upload work plan");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "upload work plan (sync)");
@@ -527,7 +544,8 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
         if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
     }
     if (c->plan.nslots > 0) {
-        e = slab ? recon::launch_reduce_partials8(jt, items, nitems, c->stream)
+        e = slab ? recon::launch_reduce_partials8(jt, items + nitems, static_cast<int>(c->plan.ritems.size()),
+                                                  c->stream)
                  : recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
     }
@@ -836,6 +854,7 @@ struct recon_batch {
     unsigned char *ws;
     size_t ws_bytes;
     int nitems;
+    int nritems;   // split tiles, stored after the items
     size_t off_items;
     int wpb, flags, inner;   // slab launch configuration of the batch
 };
@@ -901,7 +920,7 @@ recon_status recon_batch_query_size(recon_ctx *const *ctxs, int32_t njobs, size_
     std::vector<Item> items;
     recon_status st = batch_plan(ctxs, njobs, &items);
     if (st != RECON_OK) return st;
-    *ws_bytes = align_up(sizeof(Counters), 256) + align_up(items.size() * sizeof(Item), 256);
+    *ws_bytes = align_up(sizeof(Counters), 256) + align_up(2 * items.size() * sizeof(Item), 256);
     return RECON_OK;
 }
 
@@ -912,7 +931,7 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     std::vector<Item> items;
     recon_status st = batch_plan(ctxs, njobs, &items);
     if (st != RECON_OK) return st;
-    const size_t need = align_up(sizeof(Counters), 256) + align_up(items.size() * sizeof(Item), 256);
+    const size_t need = align_up(sizeof(Counters), 256) + align_up(2 * items.size() * sizeof(Item), 256);
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return fail(RECON_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return fail(RECON_ENOMEM, "batch workspace too small: %zu given, %zu needed", ws_bytes, need);
     const BatchLaunch bl = batch_launch(ctxs[0]);
@@ -931,8 +950,13 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     b->inner = bl.inner;
     hipStream_t st0 = ctxs[0]->stream;
     hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
-    if (e == hipSuccess && !items.empty())
-        e = hipMemcpyAsync(b->ws + b->off_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, st0);
+    // items, then the split tiles right after them
+    const std::vector<Item> rit = split_tiles(items);
+    b->nritems = static_cast<int>(rit.size());
+    std::vector<Item> all(items);
+    all.insert(all.end(), rit.begin(), rit.end());
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpyAsync(b->ws + b->off_items, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice, st0);
     if (e == hipSuccess) e = hipStreamSynchronize(st0);
     if (e != hipSuccess) {
         delete b;
@@ -983,7 +1007,7 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, b->flags, exact, table, items, b->nitems,
                                              b->inner, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
                                              b->wpb, bctr, st);
-    if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items, b->nitems, st);
+    if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items + b->nitems, b->nritems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");
     return RECON_OK;
 }

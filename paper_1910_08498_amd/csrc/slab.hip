@@ -735,7 +735,8 @@ hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *it
     return hipGetLastError();
 }
 
-// Adds the partial sums of split 8x8x8 tiles, in part order, into G and W.
+// Adds the partial sums of split 8x8x8 tiles, in part order, into G and W
+// (one work-group per entry of the list of split tiles).
 __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Item *__restrict__ items)
 {
     const Item item = items[blockIdx.x];
@@ -757,6 +758,8 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
     const int iz = TE * tz + (lid >> 6);
     if (!(ix <= g.h && iy < g.dim && iz < g.dim)) return;
     float re = 0.f, im = 0.f, w = 0.f;
+    // sums in part order; the loads of several parts are in flight together
+#pragma unroll 4
     for (int k = 0; k < item.nparts; ++k) {
         const float *__restrict__ pp = partials + static_cast<size_t>(item.slot + k) * 3 * TV;
         re += pp[lid];
