@@ -21,11 +21,16 @@
 //         outside the disk);
 //      3. processes the hits 64 per round, each lane evaluating the
 //         branch-free WIN x WIN window from LDS (blob table lerp from LDS)
-//         and adding its partial sums to the voxel's LDS accumulator.
+//         and adding its partial sums to the voxel's LDS accumulator; only
+//         rounds whose windows can reach the disk edge gate each cell's
+//         weight by |k| < r_max.
 //    Steps 1 and the loads of step 2 for the next slice are issued before
 //    step 3 of the current one, so the loads overlap the window evaluation.
 //  * Two-level FP32 accumulation: LDS accumulators hold at most
 //    `inner_chunk` slices before they are folded into per-lane registers.
+//    A tile split into slice ranges writes its parts' sums to partial-sum
+//    slots, added in part order by k_reduce_partials8, so results are
+//    bitwise reproducible.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -58,10 +63,12 @@ struct SlabShape {
 };
 
 // Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^20 T[N-1].
-// With i = min(floor(t), N) and w = max(T[i] + frac(t) (T[i+1] - T[i]), 0),
+// With i = min(floor(t), N) and w = clamp(T[i] + frac(t) (T[i+1] - T[i]), 0, 1),
 // t = N-1 gives exactly T[N-1], and any representable t > N-1 gives 0 (the
 // sentinel slope exceeds T[N-1] by 2^20 while frac(t) >= 2^-10 there), so the
-// blob's inclusive cut-off at d^2 = a^2 costs no compare.
+// blob's inclusive cut-off at d^2 = a^2 costs no compare.  (The table lies in
+// [0, 1], so the upper clamp never acts; the clamp is the fma's output
+// modifier.)
 __host__ __device__ inline int table_words(int N) { return (N + 2 + 3) & ~3; }
 
 __device__ __forceinline__ void wave_sync()
