@@ -106,8 +106,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the insertion shards by slices, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported (the insertion would "
+              f"shard by slices: each GPU inserts its share into its own G and W, then one sum-reduction)",
+              file=sys.stderr)
         return 2
     if args.workload == "batch8":
         return bench_batch8(args)
