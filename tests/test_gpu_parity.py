@@ -126,6 +126,32 @@ def test_blob_and_cutoff_variants(recon, torch_dev, variant, a, alpha, m, lerp, 
     assert_parity(gpu, ref)
 
 
+@pytest.mark.parametrize("variant", ["naive", "slab"])
+def test_large_boundary_weight_differs_only_by_cutoff_flips(recon, torch_dev, variant):
+    # alpha = 3: the blob keeps b(a^2) = 1/I_0(3) = 0.205 at its edge.  A
+    # sample within FP32 rounding (a few 1e-3 table steps) of the inclusive
+    # cut-off d^2 = a^2 may then be taken or left out differently from the
+    # FP64 oracle, moving W at one voxel by b(a^2) (and G by b(a^2) F(k)).
+    # Everything else must agree to the usual bar.
+    w = synth.make_workload("small", n=48, S=200, K=6, seed_phantom=11, seed_orient=12)
+    G, W, V, st = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, blob_alpha=3.0)
+    blob = oracle.Blob(alpha=3.0)
+    Go, Wo, _ = oracle.insert(w.n, w.slices, w.quats, blob=blob)
+    Vo = oracle.finalize(Go, Wo)
+    edge = blob.table()[-1]
+    dW = np.abs(W - Wo)
+    flip = dW > 0.5 * edge
+    k = dW[flip] / edge
+    print(f"   b(a^2) = {edge:.4f}; {int(flip.sum())} voxels with cut-off flips "
+          f"(of {int((Wo > 0).sum())} reached)", flush=True)
+    assert np.all(np.abs(k - np.rint(k)) < 0.01)          # whole boundary samples only
+    assert flip.sum() <= 1e-4 * (Wo > 0).sum()
+    keep = ~flip
+    assert oracle.rel_l2(W[keep], Wo[keep]) <= TOL
+    assert oracle.rel_l2(G[keep], Go[keep]) <= TOL
+    assert oracle.rel_l2(V[keep], Vo[keep]) <= TOL
+
+
 def test_truncated_table_rule(recon, torch_dev):
     # truncation: FP32 vs FP64 index decisions may differ by one table bin
     # (|T[i+1]-T[i]| <= 7.6e-4) on rare pairs; measured, looser bound
