@@ -11,7 +11,11 @@ and a 10,000-entry table.
 The headline value is slice-sample x voxel updates per second: the exact
 number of (disk sample, voxel within the blob) pairs of the workload, counted
 by the FP64 oracle and stored in tests/golden/pair_counts.json, divided by
-the measured time per step.  Printed as one JSON line.
+the measured time per step.  Printed as one JSON line, which also carries
+the roofline of the insertion kernel, the same step with the plain per-voxel
+gather ("plain", and "tuned_over_plain"), the FP64 oracle timed on a sample
+of the workload ("cpu_baseline"), and the error of the measured
+configuration against that oracle on the same sample ("error_vs_oracle").
 """
 from __future__ import annotations
 
@@ -71,18 +75,37 @@ def load_traffic(launch_count_per_step):
 
 
 def cpu_baseline(workload, n_slices: int, slices=None):
-    """The FP64 oracle on a bounded sample of the same workload."""
+    """The FP64 oracle on a bounded sample of the same workload; returns the
+    timing record and the oracle's G and W for that sample."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     sl = (workload.slices if slices is None else slices)[:n_slices]
     q = workload.quats[:n_slices]
     oracle.insert(workload.n, sl[:8], q[:8], nthreads=threads)      # load / warm
     t0 = time.perf_counter()
-    _, _, U = oracle.insert(workload.n, sl, q, nthreads=threads)
+    G, W, U = oracle.insert(workload.n, sl, q, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": U / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_slices} of {workload.S} slices of the same workload "
-                      f"({U} pairs, FP64 scatter, table lerp), {dt:.2f} s wall"}
+                      f"({U} pairs, FP64 scatter, table lerp), {dt:.2f} s wall"}, G, W
+
+
+def error_vs_oracle(rec, torch, slices, quats, scales, k: int, batch: int, V, G_o, W_o):
+    """Relative L2 error of the measured configuration against the oracle on
+    the CPU-baseline sample: the first k slices inserted into a cleared
+    volume, whole volume compared."""
+    import oracle
+    from paper_1910_08498_amd import recon
+    rec.reset()
+    for s0 in range(0, k, batch):
+        s1 = min(k, s0 + batch)
+        recon.recon_insert_batch(rec.ctx, slices[s0:s1], None if scales is None else scales[s0:s1],
+                                 quats[s0:s1], s1 - s0)
+    rec.finalize(out=V)
+    torch.cuda.synchronize()
+    G, W, Vg = rec.G.cpu().numpy(), rec.W.cpu().numpy(), V.cpu().numpy()
+    return {"G": oracle.rel_l2(G, G_o), "W": oracle.rel_l2(W, W_o), "V": oracle.rel_l2(Vg, oracle.finalize(G_o, W_o)),
+            "bound": 1e-5, "sample": f"first {k} slices, whole volume, FP64 oracle on the values the kernels read"}
 
 
 def main(argv=None):
@@ -228,10 +251,13 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = None
+    cpu = err = None
     if args.cpu_slices > 0:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, min(args.cpu_slices, w.S), cpu_slices)
+        k = min(args.cpu_slices, w.S)
+        cpu, G_o, W_o = cpu_baseline(w, k, cpu_slices)
+        err = error_vs_oracle(rec, torch, slices, quats, scales, k, args.batch, V, G_o, W_o)
+        del G_o, W_o
 
     result = {
         "metric": "slice-sample×voxel updates/s",
@@ -265,6 +291,8 @@ def main(argv=None):
         },
         "h2d_inclusive": h2d,
         "plain": plain,
+        "tuned_over_plain": None if plain is None else value / plain["value"],
+        "error_vs_oracle": err,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
