@@ -13,7 +13,7 @@ number of (disk sample, voxel within the blob) pairs of the workload, counted
 by the FP64 oracle and stored in tests/golden/pair_counts.json, divided by
 the measured time per step.  Printed as one JSON line, which also carries
 the roofline of the insertion kernel, the same step with the plain per-voxel
-gather ("plain", and "tuned_over_plain"), the FP64 oracle timed on a sample
+gather ("plain", and "default_over_plain"), the FP64 oracle timed on a sample
 of the workload ("cpu_baseline"), and the error of the measured
 configuration against that oracle on the same sample ("error_vs_oracle").
 """
@@ -74,20 +74,48 @@ def load_traffic(launch_count_per_step):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(workload, n_slices: int, slices=None):
-    """The FP64 oracle on a bounded sample of the same workload; returns the
-    timing record and the oracle's G and W for that sample."""
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu prints it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, n_slices: int, slices=None, n_single: int = 0):
+    """The FP64 oracle on a bounded sample of the same workload, on all the
+    host cores this process may use (at most 16, the host share of one GPU)
+    and, on a smaller sample, on one thread; returns the timing record and
+    the oracle's G and W for the all-core sample."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = nproc
+    threads = max(1, min(avail, 16))
     sl = (workload.slices if slices is None else slices)[:n_slices]
     q = workload.quats[:n_slices]
     oracle.insert(workload.n, sl[:8], q[:8], nthreads=threads)      # load / warm
     t0 = time.perf_counter()
     G, W, U = oracle.insert(workload.n, sl, q, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": U / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_slices} of {workload.S} slices of the same workload "
-                      f"({U} pairs, FP64 scatter, table lerp), {dt:.2f} s wall"}, G, W
+    rec = {"value": U / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_slices} of {workload.S} slices of the same workload "
+                     f"({U} pairs, FP64 scatter, table lerp), {dt:.2f} s wall",
+           "nproc": nproc, "cpu_model": cpu_model()}
+    if n_single > 0:
+        k = min(n_single, n_slices)
+        t0 = time.perf_counter()
+        _, _, U1 = oracle.insert(workload.n, sl[:k], q[:k], nthreads=1)
+        dt1 = time.perf_counter() - t0
+        rec["single_thread"] = {"value": U1 / dt1, "unit": "updates/s", "cores": 1,
+                                "sample": f"first {k} slices ({U1} pairs), {dt1:.2f} s wall"}
+    return rec, G, W
 
 
 def error_vs_oracle(rec, torch, slices, quats, scales, k: int, batch: int, V, G_o, W_o):
@@ -120,6 +148,8 @@ def main(argv=None):
                     help="slice storage: complex64, half pairs with a per-slice scale, or bfloat16 pairs")
     ap.add_argument("--cpu-slices", type=int, default=2500,
                     help="slices in the CPU-oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--cpu-single-slices", type=int, default=400,
+                    help="slices in the one-thread CPU-oracle sample (0 disables it)")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="steps timed with the naive (plain) kernel for comparison (0 disables)")
     ap.add_argument("--h2d-steps", type=int, default=2,
@@ -255,7 +285,7 @@ def main(argv=None):
     if args.cpu_slices > 0:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         k = min(args.cpu_slices, w.S)
-        cpu, G_o, W_o = cpu_baseline(w, k, cpu_slices)
+        cpu, G_o, W_o = cpu_baseline(w, k, cpu_slices, args.cpu_single_slices)
         err = error_vs_oracle(rec, torch, slices, quats, scales, k, args.batch, V, G_o, W_o)
         del G_o, W_o
 
@@ -291,7 +321,7 @@ def main(argv=None):
         },
         "h2d_inclusive": h2d,
         "plain": plain,
-        "tuned_over_plain": None if plain is None else value / plain["value"],
+        "default_over_plain": None if plain is None else value / plain["value"],
         "error_vs_oracle": err,
         "cpu_baseline": cpu,
     }

@@ -60,7 +60,7 @@ typedef enum recon_slice_dtype {
 /* Problem description.  Fill with recon_default_params() and override. */
 typedef struct recon_params {
     int32_t n;            /* slice edge; even, 4 <= n <= 1024; volume (n+1)^3 */
-    float blob_radius;    /* a, 0 < a <= 2.95 (default 1.9) */
+    float blob_radius;    /* a, 1 <= a <= 2.95 (default 1.9) */
     float blob_alpha;     /* 0 <= alpha <= 60 (default 15); alpha = 0 needs m = 0 */
     int32_t blob_order;   /* m, 0 <= m <= 8 (default 0) */
     int32_t table_size;   /* N, 2 <= N <= 65536 (default 10000) */
@@ -139,11 +139,18 @@ recon_status recon_reset(recon_ctx *ctx);
  * (recon_stats).  Only the half box x >= 0 of G and W is accumulated here;
  * recon_finalize completes the x < 0 half from Hermitian symmetry.
  * Arithmetic: weights and accumulation in FP32; each slice's rotation is
- * formed in double-float arithmetic and rounded once to FP32, and for n > 256
- * the slab kernel forms window offsets exactly (a grid part of each scaled
- * axis whose products with voxel coordinates are exact, plus a remainder),
- * so the FP32 position error does not grow with the distance from the
- * origin. */
+ * formed in double-float arithmetic and rounded once to FP32, and where
+ * positions in table units are large (n/2 sqrt((N-1)/a^2) > 6800: n > 256
+ * for the default blob) the slab kernel forms window offsets exactly (a grid
+ * part of each scaled axis whose products with voxel coordinates are exact,
+ * plus a remainder), so the FP32 position error does not grow with the
+ * distance from the origin.
+ * Accuracy: results agree with an FP64 evaluation of the same sums to
+ * 1e-5 relative L2.  A sample whose squared distance lies within FP32
+ * rounding of the cut-off a^2 may be counted or dropped differently; for
+ * blobs whose edge weight b(a^2) is not small (alpha below about 8) such a
+ * voxel differs by whole edge-weight samples, on a fraction of voxels below
+ * 1e-4, and every other voxel meets the bar. */
 recon_status recon_insert_batch(recon_ctx *ctx, const void *d_slices, const float *d_scales,
                                 const float *d_quats, int32_t count);
 
@@ -180,7 +187,7 @@ recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
  * first context's stream.  The launch uses the single-context default
  * configuration of the shared blob (11 waves per work-group for the 4 x 4
  * interpolated window, else 8), and exact window geometry for every box
- * when any box is above 256.
+ * when any box needs it (see recon_insert_batch).
  * --------------------------------------------------------------------- */
 typedef struct recon_batch recon_batch;
 

@@ -69,9 +69,11 @@ struct Orient {
 // exact geometry c = g + b with g on a grid fine enough that g . v is exact
 // for |v_i| <= 512, and b . v (|b| <= gs / 2) is added after the large part
 // has cancelled, so the error drops to an ulp of the offset itself.  It costs
-// three FMAs per coordinate and hit, so it is used where coordinates are
-// large: boxes above 256.
-inline bool exact_geometry(const Geom &g) { return g.h > 128; }
+// three FMAs per coordinate and hit, so it is used where coordinates in
+// table units are large: h sqrt((N-1)/a^2) above 6800, i.e. boxes above 256
+// for the default blob (a = 1.9, N = 10000), smaller boxes for smaller blobs
+// or larger tables (the index error of one position ulp grows with both).
+inline bool exact_geometry(const Geom &g) { return static_cast<float>(g.h) * sqrtf(g.tscale) > 6800.0f; }
 
 // Workspace counters (device, 256 bytes at the start of the workspace).
 struct Counters {

@@ -78,8 +78,10 @@ recon_status validate(const recon_params *p)
     if (!p) return fail(RECON_EINVAL, "params is NULL");
     if (p->n < 4 || p->n > 1024 || (p->n & 1))
         return fail(RECON_EINVAL, "n must be even and in [4, 1024] (got %d)", p->n);
-    if (!(p->blob_radius > 0.0f) || p->blob_radius > 2.95f)
-        return fail(RECON_EINVAL, "blob_radius must be in (0, 2.95] (got %g)", p->blob_radius);
+    // below a = 1 a voxel sees few samples (4/3 pi a^3 < 4.2 on average),
+    // so the FP32 position rounding of single samples is not averaged out
+    if (!(p->blob_radius >= 1.0f) || p->blob_radius > 2.95f)
+        return fail(RECON_EINVAL, "blob_radius must be in [1, 2.95] (got %g)", p->blob_radius);
     if (!(p->blob_alpha >= 0.0f) || !std::isfinite(p->blob_alpha) || p->blob_alpha > 60.0f)
         return fail(RECON_EINVAL, "blob_alpha must be in [0, 60] (got %g)", p->blob_alpha);
     if (p->blob_order < 0 || p->blob_order > 8)

@@ -62,13 +62,14 @@ struct SlabShape {
     static constexpr int WAVE_WORDS = slab_wave_words(WIN);
 };
 
-// Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^20 T[N-1].
+// Table in LDS: T[0..N-1], then two sentinels T[N] = T[N+1] = -2^30 T[N-1].
 // With i = min(floor(t), N) and w = clamp(T[i] + frac(t) (T[i+1] - T[i]), 0, 1),
-// t = N-1 gives exactly T[N-1], and any representable t > N-1 gives 0 (the
-// sentinel slope exceeds T[N-1] by 2^20 while frac(t) >= 2^-10 there), so the
-// blob's inclusive cut-off at d^2 = a^2 costs no compare.  (The table lies in
-// [0, 1], so the upper clamp never acts; the clamp is the fma's output
-// modifier.)
+// t = N-1 gives exactly T[N-1], and any representable t > N-1 gives 0, so the
+// blob's inclusive cut-off at d^2 = a^2 costs no compare: past N-1 >= 1 the
+// float spacing, and so frac(t), is at least 2^-23, and the sentinel slope
+// exceeds T[N-1] by 2^30, so the lerp is at most T[N-1] (1 - 2^7) < 0; from N
+// on, both sentinels give T[N] < 0.  (The table lies in [0, 1], so the upper
+// clamp never acts; the clamp is the fma's output modifier.)
 __host__ __device__ inline int table_words(int N) { return (N + 2 + 3) & ~3; }
 
 __device__ __forceinline__ void wave_sync()
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     float *tab = smem;
     for (int i = threadIdx.x; i < N; i += blockDim.x) tab[i] = table_g[i].x;
     if (threadIdx.x == 0) {
-        const float sentinel = -1048576.0f * table_g[N - 1].x;
+        const float sentinel = -1073741824.0f * table_g[N - 1].x;
         tab[N] = sentinel;
         tab[N + 1] = sentinel;
     }
@@ -820,8 +821,6 @@ static hipError_t dispatch_slab(const JobTable &jt, bool lerp, int flags, const 
                     : launch_slab_t<WV, false, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,       \
                                                                                 inner_chunk, blocks, wpb, ctr, st);
     switch (win) {
-        RECON_SLAB_CASE(1)
-        RECON_SLAB_CASE(2)
         RECON_SLAB_CASE(3)
         RECON_SLAB_CASE(4)
         RECON_SLAB_CASE(5)

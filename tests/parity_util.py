@@ -1,0 +1,60 @@
+"""Comparison helpers shared by the GPU parity tests (no GPU code here).
+
+rel_l2 over the whole box (the parity metric) and the per-voxel diagnostic:
+over the voxels that received a sizeable weight (W_o >= 1e-3 max W_o), the
+largest relative error of W and of V = G / W.  V's relative error is taken
+only where |V_o| is not tiny against the largest |V_o| of that set, since V
+passes through zero (the transform of the phantom does) and a relative error
+there says nothing about the arithmetic.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+W_FRAC = 1e-3       # voxels with W_o >= W_FRAC * max W_o
+V_FRAC = 1e-3       # ... and, for V, |V_o| >= V_FRAC * max |V_o| over them
+
+
+def errors(G, W, V, Go, Wo, Vo) -> dict:
+    """rel-L2 of G, W, V and the per-voxel maxima (see module text)."""
+    out = {"G": oracle.rel_l2(G, Go), "W": oracle.rel_l2(W, Wo), "V": oracle.rel_l2(V, Vo)}
+    Wo = np.asarray(Wo, dtype=np.float64)
+    sel = Wo >= W_FRAC * Wo.max() if Wo.size and Wo.max() > 0 else np.zeros(Wo.shape, bool)
+    if sel.any():
+        w_rel = np.abs(np.asarray(W, np.float64)[sel] - Wo[sel]) / Wo[sel]
+        vo = np.asarray(Vo, np.complex128)[sel]
+        dv = np.abs(np.asarray(V, np.complex128)[sel] - vo)
+        big = np.abs(vo) >= V_FRAC * np.abs(vo).max()
+        out["W_max_rel"] = float(w_rel.max())
+        out["V_max_rel"] = float((dv[big] / np.abs(vo[big])).max()) if big.any() else 0.0
+        out["voxels"] = int(sel.sum())
+    else:
+        out["W_max_rel"] = out["V_max_rel"] = 0.0
+        out["voxels"] = 0
+    return out
+
+
+def fmt(e: dict) -> str:
+    return (f"rel-L2 G={e['G']:.2e} W={e['W']:.2e} V={e['V']:.2e}; per voxel (W >= 1e-3 max W, "
+            f"{e['voxels']} voxels) max |dW|/W={e['W_max_rel']:.2e} max |dV|/|V|={e['V_max_rel']:.2e}")
+
+
+def cutoff_flips(W, Wo, edge: float):
+    """Voxels whose W differs from the oracle by whole blob-edge samples.
+
+    A sample within FP32 rounding of the inclusive cut-off d^2 = a^2 may be
+    taken or left out unlike the FP64 oracle; it then moves W at one voxel by
+    b(a^2) (and G by b(a^2) F).  Returns the boolean mask of such voxels when
+    the edge weight is large enough to see (else no voxel), after checking
+    that each of them differs by an integer number of edge weights."""
+    W = np.asarray(W, np.float64)
+    Wo = np.asarray(Wo, np.float64)
+    if edge <= 1e-4:
+        return np.zeros(W.shape, bool)
+    dW = np.abs(W - Wo)
+    flip = dW > 0.5 * edge
+    k = dW[flip] / edge
+    assert np.all(np.abs(k - np.rint(k)) < 0.01), "differences are not whole edge samples"
+    return flip

@@ -62,7 +62,7 @@ def test_degenerate_blob_rejected(recon):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 3.5),
+    ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 0.99), ("blob_radius", 3.5),
     ("blob_alpha", -1.0), ("blob_order", 9), ("table_size", 1), ("table_lerp", 2),
     ("r_max", 64.5), ("r_max", 0.0), ("max_batch", 0), ("slice_dtype", 7), ("slice_dtype", -1),
 ])

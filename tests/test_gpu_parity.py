@@ -1,19 +1,25 @@
 """GPU parity: the HIP insertion path (through the C ABI) against the FP64 oracle.
 
-Bar: relative L2 <= 1e-5 for G, W and V in FP32 storage and arithmetic.
-Cases span several tiles with ragged edges, batch boundaries, blob and
-cutoff variants, rejected orientations, determinism of the non-atomic path,
-repeated finalize, and the paper-scale workload (128^2 slices, 10,000 of
-them, 129^3 volume) on sampled voxels.
+Bar: relative L2 <= 1e-5 for G, W and V in FP32 storage and arithmetic, and
+per voxel (over voxels with W >= 1e-3 max W) a relative error of W and of V
+within VOXEL_W and VOXEL_V.  Cases span several tiles with ragged edges,
+batch boundaries, blob and cutoff variants (blobs with a large edge weight
+compared flip-aware), small tables, rejected orientations, determinism of
+the non-atomic path, repeated finalize, and the paper-scale workload (128^2
+slices, 10,000 of them, 129^3 volume) over the whole volume.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from parity_util import cutoff_flips, errors, fmt
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+# per-voxel bounds (voxels with W >= 1e-3 max W; V where |V| >= 1e-3 max |V|)
+VOXEL_W = 1e-3
+VOXEL_V = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -67,12 +73,28 @@ def oracle_run(n, slices, quats, **kw):
     return G, W, oracle.finalize(G, W), U
 
 
-def assert_parity(gpu, ref, tol=TOL):
+def assert_parity(gpu, ref, tol=TOL, voxel=True):
     G, W, V = gpu[:3]
     Go, Wo, Vo = ref[:3]
-    eg, ew, ev = oracle.rel_l2(G, Go), oracle.rel_l2(W, Wo), oracle.rel_l2(V, Vo)
-    print(f"   rel-L2 G={eg:.2e} W={ew:.2e} V={ev:.2e}", flush=True)
-    assert eg <= tol and ew <= tol and ev <= tol, (eg, ew, ev)
+    e = errors(G, W, V, Go, Wo, Vo)
+    print("   " + fmt(e), flush=True)
+    assert e["G"] <= tol and e["W"] <= tol and e["V"] <= tol, e
+    if voxel:
+        assert e["W_max_rel"] <= VOXEL_W and e["V_max_rel"] <= VOXEL_V, e
+
+
+def assert_parity_flips(gpu, ref, edge):
+    """Parity for blobs whose edge weight b(a^2) is visible: voxels that
+    differ by whole edge samples (cut-off decisions within FP32 rounding of
+    d^2 = a^2) are counted and bounded; every other voxel meets the bar."""
+    G, W, V = gpu[:3]
+    Go, Wo, Vo = ref[:3]
+    flip = cutoff_flips(W, Wo, edge)
+    reached = int((Wo > 0).sum())
+    print(f"   b(a^2) = {edge:.3g}: {int(flip.sum())} voxels with cut-off flips (of {reached} reached)", flush=True)
+    assert flip.sum() <= 1e-4 * reached
+    keep = ~flip
+    assert_parity((G[keep], W[keep], V[keep]), (Go[keep], Wo[keep], Vo[keep]))
 
 
 @pytest.fixture(scope="module")
@@ -107,7 +129,7 @@ def test_batch_boundaries(recon, torch_dev, S):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("a,alpha,m,lerp,r_max", [
     (1.5, 10.0, 0, 1, None), (2.5, 15.0, 0, 1, None), (2.95, 12.0, 2, 1, None),
-    (1.9, 15.0, 0, 1, 11.0), (0.8, 5.0, 0, 1, None),
+    (1.9, 15.0, 0, 1, 11.0), (1.0, 5.0, 0, 1, None),
 ])
 def test_blob_and_cutoff_variants(recon, torch_dev, variant, a, alpha, m, lerp, r_max):
     w = synth.make_workload("small", n=32, S=90, K=6, seed_phantom=5, seed_orient=6)
@@ -123,6 +145,19 @@ def test_blob_and_cutoff_variants(recon, torch_dev, variant, a, alpha, m, lerp, 
     gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, **params)
     blob = oracle.Blob(a=float(np.float32(a)), alpha=alpha, m=m, N=10000, lerp=bool(lerp))
     ref = oracle_run(w.n, w.slices, w.quats, blob=blob, r_max=r_max)
+    assert_parity_flips(gpu, ref, blob.table()[-1])
+
+
+@pytest.mark.parametrize("variant", ["naive", "binned", "slab"])
+@pytest.mark.parametrize("N", [2, 3, 8, 16])
+def test_small_tables(recon, torch_dev, variant, N):
+    # tables of a few entries: the cut-off past the last entry must hold for
+    # every t > N - 1 (the slab kernel's sentinels), and the lerp between the
+    # few entries must follow the same rule as the oracle
+    w = synth.make_workload("small", n=24, S=60, K=5, seed_phantom=20 + N, seed_orient=30 + N)
+    gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, table_size=N, max_batch=64)
+    blob = oracle.Blob(N=N)
+    ref = oracle_run(w.n, w.slices, w.quats, blob=blob)
     assert_parity(gpu, ref)
 
 
@@ -134,22 +169,9 @@ def test_large_boundary_weight_differs_only_by_cutoff_flips(recon, torch_dev, va
     # FP64 oracle, moving W at one voxel by b(a^2) (and G by b(a^2) F(k)).
     # Everything else must agree to the usual bar.
     w = synth.make_workload("small", n=48, S=200, K=6, seed_phantom=11, seed_orient=12)
-    G, W, V, st = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, blob_alpha=3.0)
+    gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant, blob_alpha=3.0)
     blob = oracle.Blob(alpha=3.0)
-    Go, Wo, _ = oracle.insert(w.n, w.slices, w.quats, blob=blob)
-    Vo = oracle.finalize(Go, Wo)
-    edge = blob.table()[-1]
-    dW = np.abs(W - Wo)
-    flip = dW > 0.5 * edge
-    k = dW[flip] / edge
-    print(f"   b(a^2) = {edge:.4f}; {int(flip.sum())} voxels with cut-off flips "
-          f"(of {int((Wo > 0).sum())} reached)", flush=True)
-    assert np.all(np.abs(k - np.rint(k)) < 0.01)          # whole boundary samples only
-    assert flip.sum() <= 1e-4 * (Wo > 0).sum()
-    keep = ~flip
-    assert oracle.rel_l2(W[keep], Wo[keep]) <= TOL
-    assert oracle.rel_l2(G[keep], Go[keep]) <= TOL
-    assert oracle.rel_l2(V[keep], Vo[keep]) <= TOL
+    assert_parity_flips(gpu, oracle_run(w.n, w.slices, w.quats, blob=blob), blob.table()[-1])
 
 
 def test_truncated_table_rule(recon, torch_dev):
@@ -158,7 +180,7 @@ def test_truncated_table_rule(recon, torch_dev):
     w = synth.make_workload("small", n=32, S=90, K=6, seed_phantom=7, seed_orient=8)
     gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, table_lerp=0)
     ref = oracle_run(w.n, w.slices, w.quats, blob=oracle.Blob(lerp=False))
-    assert_parity(gpu, ref, tol=1e-4)
+    assert_parity(gpu, ref, tol=1e-4, voxel=False)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -244,7 +266,18 @@ def paper_scale():
     return synth.make_workload("paper")
 
 
-@pytest.mark.parametrize("variant", ["binned", "slab", "slab8"])
+@pytest.mark.timeout(600)
+def test_paper_scale_whole_volume(recon, torch_dev, paper_scale):
+    # the benchmarked workload and configuration (the library default, batches
+    # of 1,500 slices), every voxel of G, W and V against the FP64 oracle
+    w = paper_scale
+    gpu = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, "slab")
+    assert gpu[3] == (w.S, 0)
+    print("   FP64 oracle over all 10,000 slices (16 threads)", flush=True)
+    assert_parity(gpu, oracle_run(w.n, w.slices, w.quats, nthreads=16))
+
+
+@pytest.mark.parametrize("variant", ["binned", "slab8"])
 def test_paper_scale_sampled_voxels(recon, torch_dev, paper_scale, variant):
     w = paper_scale
     G, W, V, stats = gpu_run(recon, torch_dev, w.n, w.slices, w.quats, variant)
