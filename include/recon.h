@@ -63,7 +63,9 @@ typedef struct recon_params {
     float blob_radius;    /* a, 1 <= a <= 2.95 (default 1.9) */
     float blob_alpha;     /* 0 <= alpha <= 60 (default 15); alpha = 0 needs m = 0 */
     int32_t blob_order;   /* m, 0 <= m <= 8 (default 0) */
-    int32_t table_size;   /* N, 2 <= N <= 65536 (default 10000) */
+    int32_t table_size;   /* N, 2 <= N <= 65536 (default 10000); 0: no table, weights on
+                             the fly (needs a blob whose series converges within 72
+                             terms: alpha up to about 60 for order 0) */
     int32_t table_lerp;   /* 1: linear interpolation in the table (default), 0: truncation */
     float r_max;          /* 0 < r_max <= n/2 (default n/2) */
     int32_t slice_dtype;  /* recon_slice_dtype (default RECON_SLICE_C64) */
@@ -101,8 +103,24 @@ typedef struct recon_config {
                                  the number of CUs the context's stream may use when that
                                  stream is restricted to a subset (a CU-masked stream).
                                  Not a tuning knob: the tuner keeps the current value */
-    int32_t reserved[9];
+    int32_t weights;          /* recon_weights: interpolation weights from the table or
+                                 evaluated on the fly (the slab variant then runs at most
+                                 8 waves and has no window preload) */
+    int32_t reserved[8];
 } recon_config;
+
+/* Source of the interpolation weights (Sect. 4.2, "3D Fourier
+ * Reconstruction": precomputed or computed on the fly).  The table holds
+ * T[i] = b(i a^2/(N-1)) built in FP64 and is read by the rule of
+ * recon_params.table_lerp; on the fly the kernels evaluate the blob itself,
+ * b = s^m sum_j c_j s^j with s = 1 - d^2/a^2 and c_j from the power series of
+ * I_m (terms until the rest is below 1e-10), by Horner's rule in FP32.  Both
+ * agree with the exact blob to about 1e-7. */
+typedef enum recon_weights {
+    RECON_WEIGHTS_DEFAULT = 0,   /* the table if table_size > 0, else on the fly */
+    RECON_WEIGHTS_TABLE = 1,
+    RECON_WEIGHTS_OTF = 2
+} recon_weights;
 
 typedef struct recon_ctx recon_ctx;
 

@@ -22,14 +22,22 @@ namespace recon {
 // small helpers
 // ---------------------------------------------------------------------------
 
-// Tabulated blob: t = d^2 (N-1)/a^2 >= 0; entry i holds (T[i], T[i+1]-T[i]).
-template <bool LERP>
-__device__ __forceinline__ float blob_lookup(const float2 *__restrict__ tab, float t, int N)
+// Blob weight at squared distance d2 <= a^2.  Table modes: t = d^2 (N-1)/a^2,
+// entry i of `tab` holds (T[i], T[i+1]-T[i]).  On-the-fly mode: `tab` holds
+// the polynomial's coefficients, evaluated at s = 1 - d^2/a^2 (clamped at 0,
+// where rounding leaves a tiny negative s for d2 = a^2).
+template <int MODE>
+__device__ __forceinline__ float blob_weight(const float2 *__restrict__ tab, float d2, const Geom &g)
 {
-    const int i = min(static_cast<int>(t), N - 1);
-    const float2 e = tab[i];
-    if (LERP) return fmaf(t - static_cast<float>(i), e.y, e.x);
-    return e.x;
+    if constexpr (MODE == WEIGHT_OTF) {
+        return blob_poly(tab, g.nterms, fmaxf(fmaf(-d2, g.inv_a2, 1.0f), 0.0f));
+    } else {
+        const float t = d2 * g.tscale;
+        const int i = min(static_cast<int>(t), g.N - 1);
+        const float2 e = tab[i];
+        if (MODE == WEIGHT_LERP) return fmaf(t - static_cast<float>(i), e.y, e.x);
+        return e.x;
+    }
 }
 
 // Full-plane sample F~(k) from the stored half plane of one slice.
@@ -53,7 +61,7 @@ __device__ __forceinline__ const unsigned char *slice_base(const void *slices, i
 __device__ __forceinline__ float slice_scale(int s, const Geom &g) { return g.scales ? g.scales[s] : 1.0f; }
 
 // Accumulates the WIN x WIN window of one (voxel, slice) pair.
-template <int WIN, bool LERP>
+template <int WIN, int MODE>
 __device__ __forceinline__ void window_global(const unsigned char *__restrict__ Fs, float scale, const Geom &g,
                                               const float2 *__restrict__ tab, float ux, float uy,
                                               float uz, float &pr, float &pi, float &pw)
@@ -73,7 +81,7 @@ __device__ __forceinline__ void window_global(const unsigned char *__restrict__ 
             const float d2 = fmaf(dx, dx, dyz);
             const bool in_disk = static_cast<float>(kx * kx + ky * ky) < g.r2max;
             if (d2 <= g.a2 && in_disk) {
-                const float w = blob_lookup<LERP>(tab, d2 * g.tscale, g.N);
+                const float w = blob_weight<MODE>(tab, d2, g);
                 const float2 f = fetch_full(Fs, scale, g, kx, ky);
                 pr = fmaf(w, f.x, pr);
                 pi = fmaf(w, f.y, pi);
@@ -259,7 +267,7 @@ hipError_t launch_prep(const float *quats, int count, float tscale, bool exact, 
 // ---------------------------------------------------------------------------
 // naive gather: one thread per voxel of the half box, every slice
 // ---------------------------------------------------------------------------
-template <int WIN, bool LERP>
+template <int WIN, int MODE>
 __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const void *__restrict__ slices,
                                                        const Orient *__restrict__ orient, int count,
                                                        const float2 *__restrict__ tab, int inner_chunk,
@@ -287,7 +295,7 @@ __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const void *__res
         if (fabsf(uz) <= g.a) {
             const float ux = fmaf(o.e1.x, vx, fmaf(o.e1.y, vy, o.e1.z * vz));
             const float uy = fmaf(o.e2.x, vx, fmaf(o.e2.y, vy, o.e2.z * vz));
-            window_global<WIN, LERP>(slice_base(slices, s, g), slice_scale(s, g), g, tab, ux, uy, uz, ire, iim,
+            window_global<WIN, MODE>(slice_base(slices, s, g), slice_scale(s, g), g, tab, ux, uy, uz, ire, iim,
                                      iw);
         }
         if (++inner == inner_chunk) {
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_insert_naive(Geom g, const void *__res
     W[vi] += ow;
 }
 
-template <int WIN, bool LERP>
+template <int WIN, int MODE>
 static hipError_t launch_naive_t(const Geom &g, const void *slices, const Orient *orient, int count,
                                  const float2 *tab, int inner_chunk, int wpb, float2 *G, float *W,
                                  hipStream_t st)
@@ -313,25 +321,31 @@ static hipError_t launch_naive_t(const Geom &g, const void *slices, const Orient
     const long total = static_cast<long>(g.h + 1) * g.dim * g.dim;
     const int threads = 64 * wpb;
     const long blocks = (total + threads - 1) / threads;
-    hipLaunchKernelGGL((k_insert_naive<WIN, LERP>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(threads), 0, st, g, slices, orient, count, tab, inner_chunk, G, W);
+    // on the fly: the coefficients follow the table's N entries
+    const float2 *w = MODE == WEIGHT_OTF ? tab + g.N : tab;
+    hipLaunchKernelGGL((k_insert_naive<WIN, MODE>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(threads), 0, st, g, slices, orient, count, w, inner_chunk, G, W);
     return hipGetLastError();
 }
 
-#define RECON_DISPATCH_WIN(WINV, FN, ...)                                  \
-    switch (WINV) {                                                        \
-    case 1: return lerp ? FN<1, true>(__VA_ARGS__) : FN<1, false>(__VA_ARGS__); \
-    case 2: return lerp ? FN<2, true>(__VA_ARGS__) : FN<2, false>(__VA_ARGS__); \
-    case 3: return lerp ? FN<3, true>(__VA_ARGS__) : FN<3, false>(__VA_ARGS__); \
-    case 4: return lerp ? FN<4, true>(__VA_ARGS__) : FN<4, false>(__VA_ARGS__); \
-    case 5: return lerp ? FN<5, true>(__VA_ARGS__) : FN<5, false>(__VA_ARGS__); \
-    case 6: return lerp ? FN<6, true>(__VA_ARGS__) : FN<6, false>(__VA_ARGS__); \
-    default: return hipErrorInvalidValue;                                  \
+// window sizes of blob radii in [1, 2.95]: floor(2a) + 1 = 3 .. 6
+#define RECON_DISPATCH_MODE(WV, FN, ...)                                                  \
+    case WV:                                                                              \
+        return mode == WEIGHT_OTF    ? FN<WV, WEIGHT_OTF>(__VA_ARGS__)                    \
+               : mode == WEIGHT_LERP ? FN<WV, WEIGHT_LERP>(__VA_ARGS__)                   \
+                                     : FN<WV, WEIGHT_TRUNC>(__VA_ARGS__);
+#define RECON_DISPATCH_WIN(WINV, FN, ...)          \
+    switch (WINV) {                                \
+        RECON_DISPATCH_MODE(3, FN, __VA_ARGS__)    \
+        RECON_DISPATCH_MODE(4, FN, __VA_ARGS__)    \
+        RECON_DISPATCH_MODE(5, FN, __VA_ARGS__)    \
+        RECON_DISPATCH_MODE(6, FN, __VA_ARGS__)    \
+    default: return hipErrorInvalidValue;          \
     }
 
 static inline int window_size(float a) { return static_cast<int>(floorf(2.0f * a)) + 1; }
 
-hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices, const Orient *orient,
+hipError_t launch_insert_naive(const Geom &g, int mode, const void *slices, const Orient *orient,
                                int count, const float2 *table, int inner_chunk, int waves_per_block,
                                float2 *G, float *W, hipStream_t st)
 {
@@ -346,15 +360,20 @@ hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices, con
 // (ballot), then every lane (one voxel) gathers from the slices that pass.
 // The blob table lives in LDS, shared by the work-group's waves.
 // ---------------------------------------------------------------------------
-template <int WIN, bool LERP>
+template <int WIN, int MODE>
 __global__ __launch_bounds__(1024) void k_insert_binned(
     Geom g, const void *__restrict__ slices, const Orient *__restrict__ orient, int count,
     const float2 *__restrict__ table_g, const Item *__restrict__ items, int nitems,
     float4 *__restrict__ partials, int inner_chunk, Counters *__restrict__ ctr,
     float2 *__restrict__ G, float *__restrict__ W)
 {
+    // the table, or on the fly the polynomial's coefficients (after the table)
     extern __shared__ float2 tab[];
-    for (int i = threadIdx.x; i < g.N; i += blockDim.x) tab[i] = table_g[i];
+    if constexpr (MODE == WEIGHT_OTF) {
+        for (int i = threadIdx.x; i < g.nterms; i += blockDim.x) tab[i] = table_g[g.N + i];
+    } else {
+        for (int i = threadIdx.x; i < g.N; i += blockDim.x) tab[i] = table_g[i];
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -412,7 +431,7 @@ __global__ __launch_bounds__(1024) void k_insert_binned(
                 if (in_box && fabsf(uz) <= g.a) {
                     const float ux = fmaf(o.e1.x, vx, fmaf(o.e1.y, vy, o.e1.z * vz));
                     const float uy = fmaf(o.e2.x, vx, fmaf(o.e2.y, vy, o.e2.z * vz));
-                    window_global<WIN, LERP>(slice_base(slices, ss, g), slice_scale(ss, g), g, tab, ux, uy, uz, ire,
+                    window_global<WIN, MODE>(slice_base(slices, ss, g), slice_scale(ss, g), g, tab, ux, uy, uz, ire,
                                              iim, iw);
                 }
                 if (++inner == inner_chunk) {
@@ -438,19 +457,19 @@ __global__ __launch_bounds__(1024) void k_insert_binned(
     }
 }
 
-template <int WIN, bool LERP>
+template <int WIN, int MODE>
 static hipError_t launch_binned_t(const Geom &g, const void *slices, const Orient *orient, int count,
                                   const float2 *table, const Item *items, int nitems, float4 *partials,
                                   int inner_chunk, int blocks, int wpb, Counters *ctr, float2 *G,
                                   float *W, hipStream_t st)
 {
-    const size_t lds = static_cast<size_t>(g.N) * sizeof(float2);
-    hipLaunchKernelGGL((k_insert_binned<WIN, LERP>), dim3(blocks), dim3(64 * wpb), lds, st, g, slices,
+    const size_t lds = static_cast<size_t>(MODE == WEIGHT_OTF ? g.nterms : g.N) * sizeof(float2);
+    hipLaunchKernelGGL((k_insert_binned<WIN, MODE>), dim3(blocks), dim3(64 * wpb), lds, st, g, slices,
                        orient, count, table, items, nitems, partials, inner_chunk, ctr, G, W);
     return hipGetLastError();
 }
 
-hipError_t launch_insert_binned(const Geom &g, bool lerp, const void *slices, const Orient *orient,
+hipError_t launch_insert_binned(const Geom &g, int mode, const void *slices, const Orient *orient,
                                 int count, const float2 *table, const Item *items, int nitems,
                                 float4 *partials, int inner_chunk, int blocks, int waves_per_block,
                                 Counters *ctr, float2 *G, float *W, hipStream_t st)

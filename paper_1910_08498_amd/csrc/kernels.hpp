@@ -20,7 +20,36 @@ struct Geom {
     float r2max;    // r_max^2 : samples with kx^2 + ky^2 < r2max are inserted
     int dtype;      // slice storage: 0 complex64, 1 half pairs x per-slice scale, 2 bfloat16 pairs
     const float *scales;  // per-slice scales of the current batch (half storage), else NULL
+    int nterms;     // on-the-fly weights: coefficients of the blob polynomial (a multiple of 4)
+    float inv_a2;   // 1 / a^2
 };
+
+// Source of the interpolation weights (the paper's "precomputed or on the
+// fly" option, Sect. 4.2 "3D Fourier Reconstruction").
+//   WEIGHT_TRUNC, WEIGHT_LERP: the FP64-built table T[i] = b(i a^2/(N-1)),
+//     looked up at t = d^2 (N-1)/a^2 by truncation or linear interpolation;
+//   WEIGHT_OTF: the blob itself, b = s^m sum_j c_j s^j with s = 1 - d^2/a^2
+//     (the power series of I_m, divided by I_m(alpha)), evaluated by Horner's
+//     rule in FP32.  The coefficients c (nterms of them, leading ones of the
+//     highest degree padded with zeros) follow the table in the workspace.
+constexpr int WEIGHT_TRUNC = 0;
+constexpr int WEIGHT_LERP = 1;
+constexpr int WEIGHT_OTF = 2;
+constexpr int kMaxTerms = 72;   // coefficients of the on-the-fly polynomial, at most
+
+// Horner's rule over the polynomial's coefficients c[0..nterms-1] (c[0] the
+// constant term; stored as the .x of float2 entries), four at a time.
+__device__ __forceinline__ float blob_poly(const float2 *__restrict__ c, int nterms, float s)
+{
+    float acc = 0.f;
+    for (int j = nterms - 4; j >= 0; j -= 4) {
+        acc = fmaf(acc, s, c[j + 3].x);
+        acc = fmaf(acc, s, c[j + 2].x);
+        acc = fmaf(acc, s, c[j + 1].x);
+        acc = fmaf(acc, s, c[j].x);
+    }
+    return acc;
+}
 
 // Bytes per stored sample for a storage type.
 __host__ __device__ inline int sample_bytes(int dtype) { return dtype == 0 ? 8 : 4; }
@@ -69,11 +98,13 @@ struct Orient {
 // exact geometry c = g + b with g on a grid fine enough that g . v is exact
 // for |v_i| <= 512, and b . v (|b| <= gs / 2) is added after the large part
 // has cancelled, so the error drops to an ulp of the offset itself.  It costs
-// three FMAs per coordinate and hit, so it is used where coordinates in
-// table units are large: h sqrt((N-1)/a^2) above 6800, i.e. boxes above 256
-// for the default blob (a = 1.9, N = 10000), smaller boxes for smaller blobs
-// or larger tables (the index error of one position ulp grows with both).
-inline bool exact_geometry(const Geom &g) { return static_cast<float>(g.h) * sqrtf(g.tscale) > 6800.0f; }
+// three FMAs per coordinate and hit, so it is used where the weight error
+// of one position ulp is large: it grows with the distance from the origin
+// over the blob radius (a weight's slope in d^2 is of order 1/a^2, and the
+// rounding of d^2 of order a ulp(|v|)), so boxes with h > 67.4 a, i.e. boxes
+// above 256 for the default blob radius 1.9, and smaller boxes for smaller
+// blobs.
+inline bool exact_geometry(const Geom &g) { return static_cast<float>(g.h) > 67.4f * g.a; }
 
 // Workspace counters (device, 256 bytes at the start of the workspace).
 struct Counters {
@@ -118,11 +149,11 @@ hipError_t launch_zero(float *p, size_t count, hipStream_t st);
 // be built for the same choice).
 hipError_t launch_prep(const float *quats, int count, float tscale, bool exact, Orient *orient, float4 *rem,
                        Counters *ctr, unsigned *queue, hipStream_t st);
-hipError_t launch_insert_naive(const Geom &g, bool lerp, const void *slices,
+hipError_t launch_insert_naive(const Geom &g, int mode, const void *slices,
                                const Orient *orient, int count, const float2 *table,
                                int inner_chunk, int waves_per_block, float2 *G, float *W,
                                hipStream_t st);
-hipError_t launch_insert_binned(const Geom &g, bool lerp, const void *slices,
+hipError_t launch_insert_binned(const Geom &g, int mode, const void *slices,
                                 const Orient *orient, int count, const float2 *table,
                                 const Item *items, int nitems, float4 *partials,
                                 int inner_chunk, int blocks, int waves_per_block,
@@ -131,8 +162,8 @@ hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   const float4 *partials, float2 *G, float *W,
                                   hipStream_t st);
 // Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
-size_t slab_lds_bytes(const Geom &g, int waves_per_block);
-hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, bool exact, const float2 *table,
+size_t slab_lds_bytes(const Geom &g, int mode, int waves_per_block);
+hipError_t launch_insert_slab(const JobTable &jt, int mode, int flags, bool exact, const float2 *table,
                               const Item *items, int nitems, int inner_chunk, int blocks, int waves_per_block,
                               Counters *ctr, hipStream_t st);
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st);

@@ -73,6 +73,38 @@ double kb_blob(double d2, double a, double alpha, int m)
     return scale * bessel_i(m, alpha * std::sqrt(s)) / bessel_i(m, alpha);
 }
 
+// Coefficients of the blob as a polynomial in s = 1 - d^2/a^2, built in FP64:
+// b = s^(m/2) I_m(alpha sqrt(s)) / I_m(alpha) = s^m sum_j c_j s^j with
+// c_j = (alpha/2)^(2j+m) / (j! (j+m)! I_m(alpha)) (the power series of I_m,
+// whose terms carry s^(j + m/2)).  Output: out[k] = coefficient of s^k, m
+// leading zeros, terms until the rest sums below 1e-10 (b <= 1 on [0, 1], all
+// terms positive), zero-padded to a multiple of 4.  Returns the count, or 0
+// if more than kMaxTerms would be needed (a very large alpha).
+int blob_coefficients(double alpha, int m, std::vector<double> *out)
+{
+    std::vector<double> c(m, 0.0);
+    const double half = 0.5 * alpha;
+    double term = 1.0;                                  // (alpha/2)^m / m!
+    for (int j = 1; j <= m; ++j) term *= half / j;
+    const double norm = bessel_i(m, alpha);
+    bool converged = false;
+    for (int j = 0; m + j < recon::kMaxTerms; ++j) {
+        if (j > 0) term *= half * half / (static_cast<double>(j) * (j + m));
+        c.push_back(term / norm);
+        // the remaining terms shrink at least geometrically with this ratio
+        // once j (j + m) exceeds (alpha/2)^2
+        const double ratio = half * half / ((j + 1.0) * (j + 1.0 + m));
+        if (ratio < 0.5 && term / norm * ratio / (1.0 - ratio) < 1e-10) {
+            converged = true;
+            break;
+        }
+    }
+    while (c.size() % 4) c.push_back(0.0);
+    if (!converged || static_cast<int>(c.size()) > recon::kMaxTerms) return 0;
+    *out = c;
+    return static_cast<int>(c.size());
+}
+
 recon_status validate(const recon_params *p)
 {
     if (!p) return fail(RECON_EINVAL, "params is NULL");
@@ -88,8 +120,13 @@ recon_status validate(const recon_params *p)
         return fail(RECON_EINVAL, "blob_order must be in [0, 8] (got %d)", p->blob_order);
     if (p->blob_alpha == 0.0f && p->blob_order > 0)
         return fail(RECON_EINVAL, "blob_alpha 0 needs blob_order 0 (I_m(0) = 0 cannot normalise the blob)");
-    if (p->table_size < 2 || p->table_size > 65536)
-        return fail(RECON_EINVAL, "table_size must be in [2, 65536] (got %d)", p->table_size);
+    if (p->table_size != 0 && (p->table_size < 2 || p->table_size > 65536))
+        return fail(RECON_EINVAL, "table_size must be 0 (weights on the fly) or in [2, 65536] (got %d)",
+                    p->table_size);
+    std::vector<double> coef;
+    if (p->table_size == 0 && blob_coefficients(p->blob_alpha, p->blob_order, &coef) == 0)
+        return fail(RECON_EINVAL, "weights on the fly need at most %d polynomial terms (alpha %g, order %d is "
+                                  "too steep); use a table", recon::kMaxTerms, p->blob_alpha, p->blob_order);
     if (p->table_lerp != 0 && p->table_lerp != 1)
         return fail(RECON_EINVAL, "table_lerp must be 0 or 1");
     if (!(p->r_max > 0.0f) || p->r_max > 0.5f * p->n)
@@ -183,8 +220,9 @@ Layout layout_for(const recon_params &p, int nitems, size_t partial_vox)
     size_t off = 0;
     L.ctr = off;
     off = align_up(off + sizeof(Counters), 256);
+    // the blob table (N entries), then the on-the-fly polynomial's coefficients
     L.table = off;
-    off = align_up(off + static_cast<size_t>(p.table_size) * sizeof(float2), 256);
+    off = align_up(off + (static_cast<size_t>(p.table_size) + recon::kMaxTerms) * sizeof(float2), 256);
     // orientation records, then the exact-geometry axis remainders (3 float4
     // per slice)
     L.orient = off;
@@ -225,10 +263,28 @@ int default_waves(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 16; 
 
 // The slab kernel's 11-wave instance exists for the 4 x 4 window (blob
 // radius in [1.5, 2)) with table interpolation, and needs its LDS to fit.
-bool slab_wide_ok(const recon::Geom &g, bool lerp, size_t max_lds)
+bool slab_wide_ok(const recon::Geom &g, int mode, size_t max_lds)
 {
     const int win = static_cast<int>(std::floor(2.0f * g.a)) + 1;
-    return win == 4 && lerp && recon::slab_lds_bytes(g, 11) <= max_lds;
+    return win == 4 && mode == recon::WEIGHT_LERP && recon::slab_lds_bytes(g, mode, 11) <= max_lds;
+}
+
+// Weight source of a configuration: RECON_WEIGHTS_DEFAULT means the table
+// when the parameters build one, else on the fly.
+int weight_source(const recon_params &p, int weights)
+{
+    if (weights == RECON_WEIGHTS_OTF || (weights == RECON_WEIGHTS_DEFAULT && p.table_size == 0))
+        return recon::WEIGHT_OTF;
+    return p.table_lerp ? recon::WEIGHT_LERP : recon::WEIGHT_TRUNC;
+}
+
+// Geometry as the kernels of a weight source see it: on the fly, positions
+// are scaled by 1/a (squared distances in units of a^2), not in table steps.
+recon::Geom launch_geom(const recon::Geom &g, int mode)
+{
+    recon::Geom r = g;
+    if (mode == recon::WEIGHT_OTF) r.tscale = r.inv_a2;
+    return r;
 }
 
 // State of a dynamic-tuning search (random search over the tuning space).
@@ -391,12 +447,20 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->g.a = p->blob_radius;
     c->g.a2 = p->blob_radius * p->blob_radius;
     c->g.N = p->table_size;
-    c->g.tscale = static_cast<float>((p->table_size - 1) /
-                                     (static_cast<double>(p->blob_radius) * p->blob_radius));
+    const double a = p->blob_radius;
+    // table steps per unit squared distance (on the fly: none, positions in units of a)
+    c->g.tscale = p->table_size > 0 ? static_cast<float>((p->table_size - 1) / (a * a))
+                                    : static_cast<float>(1.0 / (a * a));
+    c->g.inv_a2 = static_cast<float>(1.0 / (a * a));
     c->g.r2max = p->r_max * p->r_max;
     c->g.dtype = p->slice_dtype;
     c->g.scales = nullptr;
-    if (slab_wide_ok(c->g, p->table_lerp != 0, c->max_lds)) {
+    // the blob as a polynomial in s = 1 - d^2/a^2, for weights on the fly
+    std::vector<double> coef;
+    c->g.nterms = blob_coefficients(p->blob_alpha, p->blob_order, &coef);   // > 0 if table_size == 0 (validated)
+    const int mode = weight_source(*p, RECON_WEIGHTS_DEFAULT);
+    if (mode == recon::WEIGHT_OTF) c->cfg.slab_flags = 4;   // no window preload on the fly
+    if (slab_wide_ok(c->g, mode, c->max_lds)) {
         // three waves per SIMD where the 11-wave instance applies (the
         // fastest measured configuration for the 4 x 4 window)
         c->cfg.waves_per_block = 11;
@@ -404,7 +468,7 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
         c->cfg.inner_chunk = 64;
         c->cfg.split = 32;
     }
-    if (recon::slab_lds_bytes(c->g, c->cfg.waves_per_block) > c->max_lds) {
+    if (recon::slab_lds_bytes(c->g, mode, c->cfg.waves_per_block) > c->max_lds) {
         // blob table too large for the slab kernel's LDS budget
         c->cfg.variant = static_cast<size_t>(p->table_size) * sizeof(float2) <= c->max_lds ? RECON_VARIANT_BINNED
                                                                                              : RECON_VARIANT_NAIVE;
@@ -414,17 +478,18 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     c->L = worst_layout(*p);
     c->plan = make_plan(*p, c->cfg.split, tile_edge(c->cfg.variant));
 
-    // blob table: entry i = (T[i], T[i+1] - T[i]), T[i] = b(i a^2 / (N-1)), built in FP64
+    // blob table: entry i = (T[i], T[i+1] - T[i]), T[i] = b(i a^2 / (N-1)), built in FP64;
+    // then the polynomial's coefficients (coefficient, 0)
     const int N = p->table_size;
     std::vector<double> T(N);
-    const double a = p->blob_radius;
     for (int i = 0; i < N; ++i)
         T[i] = kb_blob(static_cast<double>(i) * a * a / (N - 1), a, p->blob_alpha, p->blob_order);
-    std::vector<float2> tab(N);
+    std::vector<float2> tab(N + recon::kMaxTerms, make_float2(0.f, 0.f));
     for (int i = 0; i < N; ++i) {
         const double next = i + 1 < N ? T[i + 1] : T[i];
         tab[i] = make_float2(static_cast<float>(T[i]), static_cast<float>(next - T[i]));
     }
+    for (int k = 0; k < c->g.nterms; ++k) tab[N + k] = make_float2(static_cast<float>(coef[k]), 0.f);
     e = hipMemcpyAsync(c->ws + c->L.table, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice,
                        c->stream);
     if (e != hipSuccess) { delete c; return hip_fail(e, "upload blob table"); }
@@ -495,8 +560,10 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     float4 *rem = orient_rem(c);
     const float2 *table = reinterpret_cast<const float2 *>(c->ws + c->L.table);
     const void *slices = d_slices;
-    const bool exact = recon::exact_geometry(c->g);
-    hipError_t e = recon::launch_prep(d_quats, count, c->g.tscale, exact, orient, rem, ctr, &ctr->queue, c->stream);
+    const int mode = weight_source(c->p, c->cfg.weights);
+    const recon::Geom g = launch_geom(c->g, mode);
+    const bool exact = recon::exact_geometry(g);
+    hipError_t e = recon::launch_prep(d_quats, count, g.tscale, exact, orient, rem, ctr, &ctr->queue, c->stream);
     if (e != hipSuccess) return hip_fail(e, "prep kernel launch");
     if (c->ev_start) {
         e = hipEventRecord(c->ev_start, c->stream);
@@ -507,7 +574,7 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
         if (e != hipSuccess) return hip_fail(e, "record tuning start event");
     }
     if (c->cfg.variant == RECON_VARIANT_NAIVE) {
-        e = recon::launch_insert_naive(c->g, c->p.table_lerp != 0, slices, orient, count, table,
+        e = recon::launch_insert_naive(g, mode, slices, orient, count, table,
                                        c->cfg.inner_chunk, c->cfg.waves_per_block, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "naive insert kernel launch");
         if (c->ev_stop) {
@@ -529,11 +596,11 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
     if (slab) {
         std::memset(&jt, 0, sizeof(jt));
         jt.njobs = 1;
-        jt.job[0] = {c->g, slices, orient, rem, partials, c->G, c->W, count, 0};
-        e = recon::launch_insert_slab(jt, c->p.table_lerp != 0, c->cfg.slab_flags & 3, exact, table, items, nitems,
+        jt.job[0] = {g, slices, orient, rem, partials, c->G, c->W, count, 0};
+        e = recon::launch_insert_slab(jt, mode, c->cfg.slab_flags & 3, exact, table, items, nitems,
                                       c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->stream);
     } else
-        e = recon::launch_insert_binned(c->g, c->p.table_lerp != 0, slices, orient, count, table, items, nitems,
+        e = recon::launch_insert_binned(g, mode, slices, orient, count, table, items, nitems,
                                         partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
                                         c->W, c->stream);
     if (e != hipSuccess) return hip_fail(e, "insert kernel launch");
@@ -574,9 +641,19 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     recon_config d = default_config();
     recon_config n = cfg ? *cfg : d;
     if (n.variant == RECON_VARIANT_AUTO) n.variant = d.variant;
-    const bool wide = n.variant == RECON_VARIANT_SLAB && slab_wide_ok(c->g, c->p.table_lerp != 0, c->max_lds);
+    if (n.weights < RECON_WEIGHTS_DEFAULT || n.weights > RECON_WEIGHTS_OTF)
+        return fail(RECON_ECONFIG, "weights must be 0 (default), 1 (table) or 2 (on the fly)");
+    if (n.weights == RECON_WEIGHTS_DEFAULT) n.weights = c->p.table_size > 0 ? RECON_WEIGHTS_TABLE : RECON_WEIGHTS_OTF;
+    if (n.weights == RECON_WEIGHTS_TABLE && c->p.table_size == 0)
+        return fail(RECON_ECONFIG, "table weights need table_size > 0");
+    if (n.weights == RECON_WEIGHTS_OTF && c->g.nterms == 0)
+        return fail(RECON_ECONFIG, "weights on the fly need at most %d polynomial terms (alpha %g, order %d)",
+                    recon::kMaxTerms, c->p.blob_alpha, c->p.blob_order);
+    const int mode = weight_source(c->p, n.weights);
+    const bool otf = mode == recon::WEIGHT_OTF;
+    const bool wide = n.variant == RECON_VARIANT_SLAB && slab_wide_ok(c->g, mode, c->max_lds);
     if (n.waves_per_block == 0) n.waves_per_block = wide ? 11 : default_waves(n.variant);
-    if (n.slab_flags == 0 && n.waves_per_block == 11) n.slab_flags = 4;
+    if (n.slab_flags == 0 && (n.waves_per_block == 11 || otf)) n.slab_flags = 4;
     if (n.group == 0) n.group = d.group;
     if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
     if (n.split == 0) n.split = d.split;
@@ -593,15 +670,17 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     if (n.group < 1 || n.group > 16) return fail(RECON_ECONFIG, "group must be in [1, 16]");
     if (n.inner_chunk < 1 || n.inner_chunk > 256) return fail(RECON_ECONFIG, "inner_chunk must be in [1, 256]");
     if (n.split < 1 || n.split > kMaxSplit) return fail(RECON_ECONFIG, "split must be in [1, %d]", kMaxSplit);
-    if (n.variant == RECON_VARIANT_BINNED &&
+    if (n.variant == RECON_VARIANT_BINNED && !otf &&
         static_cast<size_t>(c->p.table_size) * sizeof(float2) > c->max_lds)
         return fail(RECON_ECONFIG, "blob table of %d entries does not fit in LDS", c->p.table_size);
     if (n.variant == RECON_VARIANT_SLAB && wpb > 8 && !(wpb == 11 && wide))
         return fail(RECON_ECONFIG, "slab kernel runs at most 8 waves per work-group, or 11 for the 4x4 window "
                                    "with table interpolation");
-    if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, wpb) > c->max_lds)
+    if (n.variant == RECON_VARIANT_SLAB && otf && (n.slab_flags & 2))
+        return fail(RECON_ECONFIG, "the window-preload flag has no instance with weights on the fly");
+    if (n.variant == RECON_VARIANT_SLAB && recon::slab_lds_bytes(c->g, mode, wpb) > c->max_lds)
         return fail(RECON_ECONFIG, "slab kernel needs %zu bytes of LDS with %d waves (device: %zu)",
-                    recon::slab_lds_bytes(c->g, wpb), wpb, c->max_lds);
+                    recon::slab_lds_bytes(c->g, mode, wpb), wpb, c->max_lds);
     if (n.cu_count < 0 || n.cu_count > c->num_cu)
         return fail(RECON_ECONFIG, "cu_count must be in [0, %d] (got %d)", c->num_cu, n.cu_count);
     *out = n;
@@ -631,26 +710,28 @@ static std::vector<recon_config> tuning_space(const recon_ctx *c)
                                  : v == RECON_VARIANT_BINNED ? std::vector<int>{8, 16}
                                                              : std::vector<int>{4, 8, 16};
         std::vector<int> splits = v == RECON_VARIANT_NAIVE ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
-        for (int wpb : waves)
-            for (int inner : {16, 32, 64})
-                for (int sp : splits)
-                    for (int fl : (v != RECON_VARIANT_SLAB ? std::vector<int>{6}
-                                   : wpb == 11 ? std::vector<int>{4, 5}      // no window preload at 11 waves
-                                               : std::vector<int>{4, 5, 6, 7})) {
-                        recon_config in;
-                        std::memset(&in, 0, sizeof(in));
-                        in.variant = v;
-                        in.waves_per_block = wpb;
-                        in.group = 1;
-                        in.inner_chunk = inner;
-                        in.split = sp;
-                        in.slab_flags = fl;
-                        in.cu_count = c->cfg.cu_count;   // a property of the stream, not tuned
-                        recon_config r;
-                        const std::string keep = g_err;
-                        if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
-                        g_err = keep;
-                    }
+        for (int wt : {RECON_WEIGHTS_TABLE, RECON_WEIGHTS_OTF})
+            for (int wpb : waves)
+                for (int inner : {16, 32, 64})
+                    for (int sp : splits)
+                        for (int fl : (v != RECON_VARIANT_SLAB ? std::vector<int>{6}
+                                       : wpb == 11 ? std::vector<int>{4, 5}   // no window preload at 11 waves
+                                                   : std::vector<int>{4, 5, 6, 7})) {
+                            recon_config in;
+                            std::memset(&in, 0, sizeof(in));
+                            in.variant = v;
+                            in.waves_per_block = wpb;
+                            in.group = 1;
+                            in.inner_chunk = inner;
+                            in.split = sp;
+                            in.slab_flags = fl;
+                            in.weights = wt;
+                            in.cu_count = c->cfg.cu_count;   // a property of the stream, not tuned
+                            recon_config r;
+                            const std::string keep = g_err;
+                            if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
+                            g_err = keep;
+                        }
     }
     return out;
 }
@@ -859,6 +940,7 @@ struct recon_batch {
     int nritems;   // split tiles, stored after the items
     size_t off_items;
     int wpb, flags, inner;   // slab launch configuration of the batch
+    int mode;                // weight source
 };
 
 // Launch configuration of a batch (the contexts share their blob): the
@@ -869,8 +951,9 @@ struct BatchLaunch {
 };
 static BatchLaunch batch_launch(const recon_ctx *c0)
 {
-    if (slab_wide_ok(c0->g, c0->p.table_lerp != 0, c0->max_lds)) return {11, 0, 64, 32};
-    return {8, 2, 32, 32};
+    const int mode = weight_source(c0->p, RECON_WEIGHTS_DEFAULT);
+    if (slab_wide_ok(c0->g, mode, c0->max_lds)) return {11, 0, 64, 32};
+    return {8, mode == recon::WEIGHT_OTF ? 0 : 2, 32, 32};
 }
 
 // Combined work plan of a batch: every context's slab plan (split of the
@@ -938,7 +1021,8 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     if (ws_bytes < need) return fail(RECON_ENOMEM, "batch workspace too small: %zu given, %zu needed", ws_bytes, need);
     const BatchLaunch bl = batch_launch(ctxs[0]);
     for (int j = 0; j < njobs; ++j)
-        if (recon::slab_lds_bytes(ctxs[j]->g, bl.wpb) > ctxs[j]->max_lds)
+        if (recon::slab_lds_bytes(ctxs[j]->g, weight_source(ctxs[j]->p, RECON_WEIGHTS_DEFAULT), bl.wpb) >
+            ctxs[j]->max_lds)
             return fail(RECON_ECONFIG, "the slab kernel does not fit this device for context %d", j);
     recon_batch *b = new (std::nothrow) recon_batch();
     if (!b) return fail(RECON_ENOMEM, "host allocation failed");
@@ -950,6 +1034,7 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     b->wpb = bl.wpb;
     b->flags = bl.flags;
     b->inner = bl.inner;
+    b->mode = weight_source(ctxs[0]->p, RECON_WEIGHTS_DEFAULT);
     hipStream_t st0 = ctxs[0]->stream;
     hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
     // items, then the split tiles right after them
@@ -985,7 +1070,7 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
         const float *sc = d_scales ? d_scales[j] : nullptr;
         if (counts[j] > 0 && c->p.slice_dtype == RECON_SLICE_F16 && !sc)
             return fail(RECON_EINVAL, "job %d: half-precision slices need scales", j);
-        recon::Geom g = c->g;
+        recon::Geom g = launch_geom(c->g, b->mode);
         g.scales = c->p.slice_dtype == RECON_SLICE_F16 ? sc : nullptr;
         jt.job[j] = {g, d_slices[j], reinterpret_cast<const Orient *>(c->ws + c->L.orient), orient_rem(c),
                      reinterpret_cast<float4 *>(c->ws + c->L.partials), c->G, c->W, counts[j], 0};
@@ -993,11 +1078,11 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     Counters *bctr = reinterpret_cast<Counters *>(b->ws);
     // one geometry mode for the whole launch: exact if any box needs it
     bool exact = false;
-    for (int j = 0; j < nj; ++j) exact = exact || recon::exact_geometry(b->ctxs[j]->g);
+    for (int j = 0; j < nj; ++j) exact = exact || recon::exact_geometry(jt.job[j].g);
     for (int j = 0; j < nj; ++j) {
         recon_ctx *c = b->ctxs[j];
         if (counts[j] == 0 && j != 0) continue;
-        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j], c->g.tscale, exact,
+        hipError_t e = recon::launch_prep(counts[j] > 0 ? d_quats[j] : nullptr, counts[j], jt.job[j].g.tscale, exact,
                                           reinterpret_cast<Orient *>(c->ws + c->L.orient), orient_rem(c),
                                           reinterpret_cast<Counters *>(c->ws + c->L.ctr),
                                           j == 0 ? &bctr->queue : nullptr, st);
@@ -1006,7 +1091,7 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
-    hipError_t e = recon::launch_insert_slab(jt, c0->p.table_lerp != 0, b->flags, exact, table, items, b->nitems,
+    hipError_t e = recon::launch_insert_slab(jt, b->mode, b->flags, exact, table, items, b->nitems,
                                              b->inner, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
                                              b->wpb, bctr, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items + b->nitems, b->nritems, st);

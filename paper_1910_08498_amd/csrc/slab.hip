@@ -71,6 +71,12 @@ struct SlabShape {
 // on, both sentinels give T[N] < 0.  (The table lies in [0, 1], so the upper
 // clamp never acts; the clamp is the fma's output modifier.)
 __host__ __device__ inline int table_words(int N) { return (N + 2 + 3) & ~3; }
+// LDS words of the weight source: the table with its sentinels, or on the
+// fly the polynomial's coefficients (a multiple of 4, so float4 reads)
+__host__ __device__ inline int weight_words(const Geom &g, int mode)
+{
+    return mode == WEIGHT_OTF ? g.nterms : table_words(g.N);
+}
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -151,12 +157,14 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 // Window of one (voxel, slice) hit from the LDS rectangle (row stride RECT)
 // whose cell (0, 0) is sample (kx_lo, ky_lo).  The hit's coordinates arrive
 // scaled by s = sqrt(table scale), so squared distances are table positions
-// directly.  RIM: the rectangle reaches the disk edge, so each candidate's
-// |k| < r_max membership gates its weight.  PRELOAD: all LDS reads of the
-// window are issued before any is consumed.  EXACT: uxs and uys are exact
-// grid-part products and uxl, uyl the remainders' products, added once the
-// large parts have cancelled (else uxl, uyl are unused).
-template <int WIN, bool RIM, bool LERP, bool PRELOAD, bool EXACT>
+// directly (on the fly, the scale is 1/a^2: positions are d^2/a^2).  RIM: the
+// rectangle reaches the disk edge, so each candidate's |k| < r_max
+// membership gates its weight.  PRELOAD: all LDS reads of the window are
+// issued before any is consumed.  EXACT: uxs and uys are exact grid-part
+// products and uxl, uyl the remainders' products, added once the large parts
+// have cancelled (else uxl, uyl are unused).  MODE: the weight source (tab
+// holds the table, or on the fly the polynomial's coefficients).
+template <int WIN, bool RIM, int MODE, bool PRELOAD, bool EXACT>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
                                            const Geom &g, float uxs, float uxl, float uys, float uyl, float uzs,
                                            float s, float inv_s, int kx_lo, int ky_lo, float &pr, float &pi,
@@ -199,6 +207,49 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         }
     }
     float sr = 0.f, si = 0.f, sw = 0.f;
+    if constexpr (MODE == WEIGHT_OTF) {
+        // every cell's s = 1 - d^2/a^2 (clamped at 0: far cells are cut off
+        // below and must not feed large powers into Horner's rule), then the
+        // polynomial for all cells at once, four coefficients per LDS read
+        // (the same address in every lane)
+        float sv[WIN * WIN], acc[WIN * WIN];
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) {
+                sv[j * WIN + i] = fmaxf(1.0f - (dxs[i] + dys[j]), 0.f);
+                acc[j * WIN + i] = 0.f;
+            }
+        for (int c = g.nterms - 4; c >= 0; c -= 4) {
+            const float4 k4 = *reinterpret_cast<const float4 *>(tab + c);
+#pragma unroll
+            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.w);
+#pragma unroll
+            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.z);
+#pragma unroll
+            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.y);
+#pragma unroll
+            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.x);
+        }
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int i = 0; i < WIN; ++i) {
+                const int k = j * WIN + i;
+                // inclusive cut-off d^2 <= a^2
+                float w = dxs[i] + dys[j] <= 1.0f ? acc[k] : 0.f;
+                if (RIM) w = kx2[i] < rem[j] ? w : 0.f;
+                const float2 f2 = base[j * RECT + i];
+                sr = fmaf(w, f2.x, sr);
+                si = fmaf(w, f2.y, si);
+                sw += w;
+            }
+        pr = sr;
+        pi = si;
+        pw = sw;
+        return;
+    }
+    constexpr bool LERP = MODE == WEIGHT_LERP;
     auto weight = [&](float tk, float t0k, float t1k, int i, int j) {
         float w;
         if (LERP) {
@@ -274,7 +325,7 @@ constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 // MAXW: largest work-group (in waves) the instance is built for; it sets the
 // register budget (8 waves: 256 VGPRs, two waves per SIMD; 11 waves: 168
 // VGPRs, three waves on three of the four SIMDs).
-template <int WIN, bool LERP, int FLAGS, int MAXW, bool EXACT>
+template <int WIN, int MODE, int FLAGS, int MAXW, bool EXACT>
 __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
                                                      const Item *__restrict__ items, int nitems, int inner_chunk,
                                                      Counters *__restrict__ ctr)
@@ -287,11 +338,16 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     // blob parameters (and so the table) are common to every job of a launch
     const int N = jt.job[0].g.N;
     float *tab = smem;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tab[i] = table_g[i].x;
-    if (threadIdx.x == 0) {
-        const float sentinel = -1073741824.0f * table_g[N - 1].x;
-        tab[N] = sentinel;
-        tab[N + 1] = sentinel;
+    if constexpr (MODE == WEIGHT_OTF) {
+        // the polynomial's coefficients, stored after the table
+        for (int i = threadIdx.x; i < jt.job[0].g.nterms; i += blockDim.x) tab[i] = table_g[N + i].x;
+    } else {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tab[i] = table_g[i].x;
+        if (threadIdx.x == 0) {
+            const float sentinel = -1073741824.0f * table_g[N - 1].x;
+            tab[N] = sentinel;
+            tab[N + 1] = sentinel;
+        }
     }
     __syncthreads();
 
@@ -301,7 +357,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     // part, so the window's cell offsets fit the LDS instructions' offset
     // fields), then the accumulators (re, im pairs and weights), then two
     // hit lists
-    float *wregion = smem + table_words(N) + wave * SS::WAVE_WORDS;
+    float *wregion = smem + weight_words(jt.job[0].g, MODE) + wave * SS::WAVE_WORDS;
     float2 *rect = reinterpret_cast<float2 *>(wregion);
     float *accs = wregion + 2 * RECT2;
     float2 *acc_c = reinterpret_cast<float2 *>(accs);
@@ -632,10 +688,10 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                             rim_round = __ballot(fmaf(ax, ax, ay * ay) >= g.r2max) != 0ull;
                         }
                         if (rim_round)
-                            window_lds<WIN, true, LERP, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
+                            window_lds<WIN, true, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
                                                                     ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         else
-                            window_lds<WIN, false, LERP, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
+                            window_lds<WIN, false, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
                                                                      ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
                         // a voxel appears once per slice: single writer within the wave
                         if (FLAGS & SLAB_ATOMIC) {
@@ -731,14 +787,14 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     }
 }
 
-template <int WIN, bool LERP, int FLAGS, bool EXACT, int MAXW = 8>
+template <int WIN, int MODE, int FLAGS, bool EXACT, int MAXW = 8>
 hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *items, int nitems, int inner_chunk,
                          int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
-    const size_t lds = (static_cast<size_t>(table_words(jt.job[0].g.N)) +
+    const size_t lds = (static_cast<size_t>(weight_words(jt.job[0].g, MODE)) +
                         static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
     if (wpb > MAXW) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_insert_slab<WIN, LERP, FLAGS, MAXW, EXACT>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
+    hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
                        items, nitems, inner_chunk, ctr);
     return hipGetLastError();
 }
@@ -784,42 +840,58 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
 
 }  // namespace
 
-size_t slab_lds_bytes(const Geom &g, int waves_per_block)
+size_t slab_lds_bytes(const Geom &g, int mode, int waves_per_block)
 {
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
-    return (static_cast<size_t>(table_words(g.N)) +
+    return (static_cast<size_t>(weight_words(g, mode)) +
             static_cast<size_t>(waves_per_block) * slab_wave_words(win)) * sizeof(float);
 }
 
 template <bool EXACT>
-static hipError_t dispatch_slab(const JobTable &jt, bool lerp, int flags, const float2 *table, const Item *items,
+static hipError_t dispatch_slab(const JobTable &jt, int mode, int flags, const float2 *table, const Item *items,
                                 int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
     const Geom &g = jt.job[0].g;
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
+    if (mode == WEIGHT_OTF) {
+        // on the fly: 8-wave instances (at most), window reads interleaved;
+        // LDS float atomics as a knob for the common window
+        if (win == 4 && (flags & SLAB_ATOMIC))
+            return launch_slab_t<4, WEIGHT_OTF, SLAB_ATOMIC, EXACT>(jt, table, items, nitems, inner_chunk, blocks,
+                                                                    wpb, ctr, st);
+        switch (win) {
+        case 3: return launch_slab_t<3, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 4: return launch_slab_t<4, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 5: return launch_slab_t<5, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 6: return launch_slab_t<6, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    const bool lerp = mode == WEIGHT_LERP;
     // every flag combination exists for the common window (a in [1.5, 2)) with
     // linear interpolation; other windows and truncation use the default flags
     if (win == 4 && lerp && wpb > 8) {
         // three waves per SIMD: register budget of 168, window reads interleaved
         if (flags & SLAB_ATOMIC)
-            return launch_slab_t<4, true, SLAB_ATOMIC, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks,
-                                                                  wpb, ctr, st);
-        return launch_slab_t<4, true, 0, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+            return launch_slab_t<4, WEIGHT_LERP, SLAB_ATOMIC, EXACT, 11>(jt, table, items, nitems, inner_chunk,
+                                                                         blocks, wpb, ctr, st);
+        return launch_slab_t<4, WEIGHT_LERP, 0, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr,
+                                                           st);
     }
     if (win == 4 && lerp) {
         switch (flags & 3) {
-        case 0: return launch_slab_t<4, true, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 1: return launch_slab_t<4, true, 1, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 2: return launch_slab_t<4, true, 2, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        default: return launch_slab_t<4, true, 3, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 0: return launch_slab_t<4, WEIGHT_LERP, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 1: return launch_slab_t<4, WEIGHT_LERP, 1, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 2: return launch_slab_t<4, WEIGHT_LERP, 2, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        default: return launch_slab_t<4, WEIGHT_LERP, 3, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
         }
     }
-#define RECON_SLAB_CASE(WV)                                                                                   \
-    case WV:                                                                                                  \
-        return lerp ? launch_slab_t<WV, true, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,        \
-                                                                               inner_chunk, blocks, wpb, ctr, st) \
-                    : launch_slab_t<WV, false, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,       \
-                                                                                inner_chunk, blocks, wpb, ctr, st);
+#define RECON_SLAB_CASE(WV)                                                                                         \
+    case WV:                                                                                                        \
+        return lerp ? launch_slab_t<WV, WEIGHT_LERP, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,     \
+                                                                                      inner_chunk, blocks, wpb, ctr, st) \
+                    : launch_slab_t<WV, WEIGHT_TRUNC, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,    \
+                                                                                       inner_chunk, blocks, wpb, ctr, st);
     switch (win) {
         RECON_SLAB_CASE(3)
         RECON_SLAB_CASE(4)
@@ -831,13 +903,13 @@ static hipError_t dispatch_slab(const JobTable &jt, bool lerp, int flags, const 
 #undef RECON_SLAB_CASE
 }
 
-hipError_t launch_insert_slab(const JobTable &jt, bool lerp, int flags, bool exact, const float2 *table,
+hipError_t launch_insert_slab(const JobTable &jt, int mode, int flags, bool exact, const float2 *table,
                               const Item *items, int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr,
                               hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    return exact ? dispatch_slab<true>(jt, lerp, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st)
-                 : dispatch_slab<false>(jt, lerp, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+    return exact ? dispatch_slab<true>(jt, mode, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st)
+                 : dispatch_slab<false>(jt, mode, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
 }
 
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st)

@@ -43,7 +43,8 @@ CU_CHOICES = (64, 128, 192, 256)
 
 
 def config_key(c) -> tuple:
-    return (int(c.variant), int(c.waves_per_block), int(c.inner_chunk), int(c.split), int(c.slab_flags))
+    return (int(c.variant), int(c.waves_per_block), int(c.inner_chunk), int(c.split), int(c.slab_flags),
+            int(c.weights))
 
 
 @dataclass

@@ -61,6 +61,16 @@ def test_degenerate_blob_rejected(recon):
     recon.recon_query_sizes(p)
 
 
+def test_on_the_fly_weights_need_no_table(recon):
+    p = recon.recon_default_params(128)
+    _, _, ws_table = recon.recon_query_sizes(p)
+    p.table_size = 0                            # weights evaluated on the fly
+    _, _, ws_otf = recon.recon_query_sizes(p)
+    assert ws_otf < ws_table
+    p.blob_alpha, p.blob_order = 60.0, 8        # the steepest accepted blob still converges
+    recon.recon_query_sizes(p)
+
+
 @pytest.mark.parametrize("field,value", [
     ("n", 63), ("n", 2), ("n", 2048), ("blob_radius", 0.0), ("blob_radius", 0.99), ("blob_radius", 3.5),
     ("blob_alpha", -1.0), ("blob_order", 9), ("table_size", 1), ("table_lerp", 2),
