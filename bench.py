@@ -13,9 +13,12 @@ number of (disk sample, voxel within the blob) pairs of the workload, counted
 by the FP64 oracle and stored in tests/golden/pair_counts.json, divided by
 the measured time per step.  Printed as one JSON line, which also carries
 the roofline of the insertion kernel, the same step with the plain per-voxel
-gather ("plain", and "default_over_plain"), the FP64 oracle timed on a sample
-of the workload ("cpu_baseline"), and the error of the measured
-configuration against that oracle on the same sample ("error_vs_oracle").
+gather ("plain", and "default_over_plain"), the step with the configuration
+the library's dynamic tuner selects on this workload ("tuned", and
+"tuned_over_plain"), the FP64 oracle timed on a sample of the workload
+("cpu_baseline"), and the error of the measured configuration against that
+oracle on the same sample ("error_vs_oracle").  The headline value is the
+library's default configuration, untuned.
 """
 from __future__ import annotations
 
@@ -46,11 +49,9 @@ WORKLOAD_TEXT = {
                  "256x129, 45,000 Haar-uniform + 5,000 clustered views) into a 257^3 complex64 G + float32 W, "
                  "KB blob a=1.9 alpha=15 m=0, 10,000-entry table (lerp), batches of 1,500 slices",
     "batch8": "batched insertion: 8 reconstructions, boxes 64,96,128,160,192,224,256,256, slice counts "
-              "uniform in 2,000-20,000 (seed 5), FP32, one persistent slab launch per round of batches "
-              "of up to 1,500 slices per reconstruction",
+              "uniform in 2,000-20,000 (seed 5), complex64 slices, FP32, one persistent slab launch per round "
+              "of batches of up to 1,500 slices per reconstruction, configuration from the library's tuner",
 }
-BATCH8_N = (64, 96, 128, 160, 192, 224, 256, 256)
-MEAN_FOOTPRINT = 28.737   # mean voxels within a = 1.9 of a random point (estimate for the batch workload)
 
 
 def kernel_sha() -> str:
@@ -152,6 +153,8 @@ def main(argv=None):
                     help="slices in the one-thread CPU-oracle sample (0 disables it)")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="steps timed with the naive (plain) kernel for comparison (0 disables)")
+    ap.add_argument("--tune-steps", type=int, default=50,
+                    help="random-search steps of the library's tuner before the tuned leg (0 disables it)")
     ap.add_argument("--h2d-steps", type=int, default=2,
                     help="steps timed with the slices uploaded from pinned host memory (0 disables)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -259,6 +262,11 @@ def main(argv=None):
     if args.h2d_steps > 0:
         h2d = h2d_inclusive(args, torch, recon, rec, slices, quats, scales, nb, w.S, U, V)
 
+    tuned = None
+    if args.tune_steps > 0:
+        tuned = tuned_leg(args, torch, recon, rec, step, nb, w.S, slices, quats, scales, U, ms_per_step)
+        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, weights=0)
+
     plain = None
     if args.plain_steps > 0 and args.variant != "naive":
         rec.set_config(variant=recon.RECON_VARIANT_NAIVE, waves_per_block=0, slab_flags=0)
@@ -322,12 +330,42 @@ def main(argv=None):
         "h2d_inclusive": h2d,
         "plain": plain,
         "default_over_plain": None if plain is None else value / plain["value"],
+        "tuned": tuned,
+        "tuned_over_plain": None if plain is None or tuned is None else tuned["value"] / plain["value"],
         "error_vs_oracle": err,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
     rec.close()
     return 0
+
+
+def tuned_leg(args, torch, recon, rec, step, nb, S, slices, quats, scales, U, default_ms):
+    """The library's dynamic tuner on this workload: a seeded random search of
+    --tune-steps configurations, each step one real insertion call of the
+    workload's batches (non-blocking tuning), then the step timed with the
+    configuration it selected."""
+    recon.recon_tune_begin(rec.ctx, max_steps=args.tune_steps, seed=2024)
+    k = 0
+    while recon.recon_tune_get_info(rec.ctx).active:
+        b = k % nb
+        s0, s1 = b * args.batch, min(S, (b + 1) * args.batch)
+        recon.recon_insert_batch(rec.ctx, slices[s0:s1], None if scales is None else scales[s0:s1],
+                                 quats[s0:s1], s1 - s0)
+        k += 1
+    recon.recon_tune_end(rec.ctx)
+    info = recon.recon_tune_get_info(rec.ctx)
+    cfg = rec.config()
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    return {"value": U / (ms / 1e3), "ms_per_step": ms, "over_default": default_ms / ms,
+            "search": f"random search, {int(info.steps_done)} of {int(info.space_size)} configurations, "
+                      f"one insertion call each", "config": cfg}
 
 
 def h2d_inclusive(args, torch, recon, rec, slices, quats, scales, nb, S, U, V):
@@ -376,94 +414,160 @@ def h2d_inclusive(args, torch, recon, rec, slices, quats, scales, nb, S, U, V):
             "note": "slices uploaded from pinned host memory per batch, overlapped with insertion"}
 
 
-def disk_samples(n: int) -> int:
-    h = n // 2
-    k = range(-h, h + 1)
-    return sum(1 for kx in k for ky in k if kx * kx + ky * ky < h * h)
-
-
 def bench_batch8(args) -> int:
-    """Eight reconstructions of different sizes inserted by one persistent
-    launch per round (recon_batch_insert).  Slices are random complex samples
-    generated on the device (the cost depends on geometry, not on values);
-    pair counts are estimated as slices x disk samples x mean footprint."""
+    """Eight reconstructions of different box sizes inserted by one persistent
+    launch per round (recon_batch_insert), each round up to --batch slices
+    per reconstruction.  The launch configuration is the one the library's
+    tuner selects on the largest box (a random search over real insertion
+    calls), given to the batch through its first context.  The step (zero,
+    every round, finalize) is captured once in a HIP graph and replayed; the
+    same rounds with one launch per reconstruction, eager, are timed beside
+    it.  Slices are phantom projections (synth), pair counts exact
+    (tests/golden/pair_counts.json), and each reconstruction's first slices
+    are checked against the FP64 oracle."""
     import numpy as np
     import torch
 
+    import oracle
+    import synth
     from paper_1910_08498_amd import recon
 
     dev = torch.device("cuda:0")
-    rng = np.random.default_rng(5)
-    counts = [int(c) for c in rng.integers(2000, 20001, size=len(BATCH8_N))]
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(5)
+    torch.cuda.set_device(dev)
+    with open(os.path.join(ROOT, "tests", "golden", "pair_counts.json")) as f:
+        counts = json.load(f)["batch8"]
+    specs = synth.batch_specs("batch8")
+    assert [(j["n"], j["S"]) for j in counts["jobs"]] == [(sp[0], sp[1]) for sp in specs]
+    side = torch.cuda.Stream(device=dev)          # default priority; graphs are captured on it
     jobs = []
-    for n, S in zip(BATCH8_N, counts):
-        h = n // 2
-        sl = torch.view_as_complex(torch.randn((S, n, h + 1, 2), generator=gen, device=dev)).contiguous()
-        q = torch.randn((S, 4), generator=gen, device=dev)
-        rec = recon.Reconstruction(n, device=dev, max_batch=args.batch)
-        jobs.append((n, S, sl, q, rec))
-        print(f"bench: job n={n} S={S}", file=sys.stderr, flush=True)
-    ctxs = [j[4].ctx for j in jobs]
+    with torch.cuda.stream(side):
+        for spec in specs:
+            n, S, K, sp, so = spec
+            print(f"bench: job n={n} S={S}", file=sys.stderr, flush=True)
+            w = synth.make_workload("small", n=n, S=S, K=K, seed_phantom=sp, seed_orient=so)
+            rec = recon.Reconstruction(n, device=dev, stream=side, max_batch=args.batch)
+            jobs.append({"w": w, "rec": rec, "sl": torch.from_numpy(w.slices).to(dev),
+                         "q": torch.from_numpy(w.quats).to(dev)})
+    side.synchronize()
+    rounds = max((j["w"].S + args.batch - 1) // args.batch for j in jobs)
+
+    # tune on the largest box, hand the configuration to the batch's first context
+    big = max(jobs, key=lambda j: j["w"].n * j["w"].n * j["w"].S)
+    tuned_cfg = None
+    if args.tune_steps > 0:
+        rb = big["rec"]
+        recon.recon_tune_begin(rb.ctx, max_steps=args.tune_steps, seed=2024)
+        k = 0
+        while recon.recon_tune_get_info(rb.ctx).active:
+            s0 = (k * args.batch) % max(1, big["w"].S - args.batch)
+            recon.recon_insert_batch(rb.ctx, big["sl"][s0:s0 + args.batch], None, big["q"][s0:s0 + args.batch],
+                                     args.batch)
+            k += 1
+        recon.recon_tune_end(rb.ctx)
+        tuned_cfg = recon.recon_get_config(rb.ctx)
+        if tuned_cfg.variant == recon.RECON_VARIANT_SLAB:
+            recon.recon_set_config(jobs[0]["rec"].ctx, tuned_cfg)
+        side.synchronize()
+    ctxs = [j["rec"].ctx for j in jobs]
     ws = torch.empty(recon.recon_batch_query_size(ctxs), dtype=torch.uint8, device=dev)
     b = recon.recon_batch_create(ctxs, ws)
-    rounds = max((S + args.batch - 1) // args.batch for _, S, _, _, _ in jobs)
+
+    def round_args(r):
+        sls, qts, cnt = [], [], []
+        for j in jobs:
+            S = j["w"].S
+            s0, s1 = min(S, r * args.batch), min(S, (r + 1) * args.batch)
+            sls.append(j["sl"][s0:s1] if s1 > s0 else None)
+            qts.append(j["q"][s0:s1] if s1 > s0 else None)
+            cnt.append(s1 - s0)
+        return sls, qts, cnt
+
+    prepared = [round_args(r) for r in range(rounds)]
 
     def step():
         for j in jobs:
-            j[4].reset()
-        for r in range(rounds):
-            sls, qts, cnt = [], [], []
-            for n, S, sl, q, rec in jobs:
-                s0, s1 = min(S, r * args.batch), min(S, (r + 1) * args.batch)
-                sls.append(sl[s0:s1] if s1 > s0 else None)
-                qts.append(q[s0:s1] if s1 > s0 else None)
-                cnt.append(s1 - s0)
+            j["rec"].reset()
+        for sls, qts, cnt in prepared:
             recon.recon_batch_insert(b, sls, None, qts, cnt)
         for j in jobs:
-            j[4].finalize()
+            j["rec"].finalize()
 
     def step_separate():
-        # the same work with one launch per reconstruction and round
         for j in jobs:
-            j[4].reset()
-        for r in range(rounds):
-            for n, S, sl, q, rec in jobs:
-                s0, s1 = min(S, r * args.batch), min(S, (r + 1) * args.batch)
-                if s1 > s0:
-                    recon.recon_insert_batch(rec.ctx, sl[s0:s1], None, q[s0:s1], s1 - s0)
+            j["rec"].reset()
+        for sls, qts, cnt in prepared:
+            for j, sl, q, c in zip(jobs, sls, qts, cnt):
+                if c:
+                    recon.recon_insert_batch(j["rec"].ctx, sl, None, q, c)
         for j in jobs:
-            j[4].finalize()
+            j["rec"].finalize()
 
     def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for _ in range(args.warmup):
+                fn()
+            side.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            side.synchronize()
         return 1e3 * (time.perf_counter() - t0) / args.steps
 
-    ms = timed(step)
+    ms_eager = timed(step)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        step()                                     # warm state before capture
+        side.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+    side.synchronize()
+    ms = timed(graph.replay)
     ms_sep = timed(step_separate)
-    U = sum(S * disk_samples(n) * MEAN_FOOTPRINT for n, S, _, _, _ in jobs)
+    U = int(counts["U"])
+
+    # each reconstruction's first slices, through the same batched launch, against the oracle
+    k = 120
+    errs = []
+    with torch.cuda.stream(side):
+        for j in jobs:
+            j["rec"].reset()
+        sls, qts, cnt = [], [], []
+        for j in jobs:
+            sls.append(j["sl"][:k])
+            qts.append(j["q"][:k])
+            cnt.append(min(k, j["w"].S))
+        recon.recon_batch_insert(b, sls, None, qts, cnt)
+        Vs = [j["rec"].finalize() for j in jobs]
+        side.synchronize()
+    for j, V in zip(jobs, Vs):
+        w = j["w"]
+        Go, Wo, _ = oracle.insert(w.n, w.slices[:k], w.quats[:k], nthreads=16)
+        errs.append({"n": w.n, "G": oracle.rel_l2(j["rec"].G.cpu().numpy(), Go),
+                     "W": oracle.rel_l2(j["rec"].W.cpu().numpy(), Wo),
+                     "V": oracle.rel_l2(V.cpu().numpy(), oracle.finalize(Go, Wo))})
     result = {
         "metric": "slice-sample×voxel updates/s", "value": U / (ms / 1e3), "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic: random complex slice samples and orientations generated on the device",
-        "config": {"workload": WORKLOAD_TEXT["batch8"], "boxes": list(BATCH8_N), "slices": counts,
-                   "rounds_per_step": rounds, "pairs_estimated": U},
+        "data": "synthetic: seeded phantom projections (exact line integrals) and their centered DFTs, "
+                "Haar-uniform orientations, per reconstruction",
+        "config": {"workload": WORKLOAD_TEXT["batch8"], "boxes": [j["w"].n for j in jobs],
+                   "slices": [j["w"].S for j in jobs], "rounds_per_step": rounds, "pairs_U": U,
+                   "launch": "one captured HIP graph per step, replayed",
+                   "batch_config": None if tuned_cfg is None else
+                   {k2: getattr(tuned_cfg, k2) for k2, _ in recon.recon_config._fields_ if k2 != "reserved"},
+                   "tuned_on": f"n={big['w'].n}, {args.tune_steps} random-search steps"},
+        "eager": {"value": U / (ms_eager / 1e3), "ms_per_step": ms_eager},
         "separate_launches": {"value": U / (ms_sep / 1e3), "ms_per_step": ms_sep,
                               "launches_per_round": len(jobs)},
+        "error_vs_oracle": {"per_job": errs, "bound": 1e-5,
+                            "sample": f"first {k} slices of each reconstruction, one batched launch, whole volumes"},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)
     recon.recon_batch_destroy(b)
     for j in jobs:
-        j[4].close()
+        j["rec"].close()
     return 0
 
 

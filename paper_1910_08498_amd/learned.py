@@ -8,21 +8,32 @@ every configuration of the tuning space on each of them, turns timings into
 target distributions, and measures the regret of the predicted configuration
 against the fastest measured one (exhaustive search).
 
-Features of a workload: log2(n), log2(slices), blob radius a, and the
-fraction of the device's compute units the reconstruction may use.  The
-last one is varied on the one device available by running the timings on a
-CU-masked stream (hipExtStreamCreateWithCUMask) with the library's cu_count
-set to match.
+Features of a workload: log2(n), log2 of the slices per kernel call (the
+library inserts batches of up to 1,500 slices, so only workloads of fewer
+slices differ), blob radius a, and the fraction of the device's compute
+units the reconstruction may use.  The last one is varied on the one device
+available by running the timings on a CU-masked stream
+(hipExtStreamCreateWithCUMask) with the library's cu_count set to match.
+
+Each configuration is timed as the median of several calls, each call a
+whole recon_insert_batch (orientation prep, insertion and the partial-sum
+reduction of split tiles, whose cost the split knob changes), at the batch
+size the library runs.  The predictor's classes are the slab-kernel
+configurations with table weights: the other variants and weights on the
+fly never win on this device, and leaving them out keeps the timing
+collection short.
 
 The predictor ranks the configurations; at run time the library's tuner
-then measures its top candidates on real work (recon_tune_begin with a
-candidate order) and keeps the fastest, which also measures how far the
-top-1 prediction was from the best candidate.  When the predictor is not
+then measures its top candidates, and the library's default configuration,
+on real work (recon_tune_begin with a candidate order) and keeps the
+fastest, which also measures how far the top-1 prediction was from the best
+candidate.  With the default among the candidates the guided search is never
+worse than running the default, up to timing noise.  When the predictor is not
 confident (top probability below a threshold) the tuner falls back to its
 random search.
 
 Configurations are identified by their knob values (variant, waves per
-work-group, inner chunk, split, slab flags).  The runnable set depends on the
+work-group, inner chunk, split, slab flags, weight source).  The runnable set depends on the
 workload (some kernel instances exist only for some blob windows), so the
 predictor scores the union of the configurations seen in training and only
 runnable ones are chosen for a workload.
@@ -40,6 +51,12 @@ from . import recon
 
 N_HIDDEN = 64
 CU_CHOICES = (64, 128, 192, 256)
+CALL_SLICES = 1500          # the library's default batch (slices per kernel call)
+
+
+def features(n: int, slices: int, a: float, cu_frac: float) -> np.ndarray:
+    """Workload features: log2 n, log2 slices per call, blob radius, CU fraction."""
+    return np.array([math.log2(n), math.log2(min(slices, CALL_SLICES)), a, cu_frac], dtype=np.float64)
 
 
 def config_key(c) -> tuple:
@@ -60,8 +77,7 @@ class TuneRecord:
     cus_total: int = 256                # compute units of the device
 
     def features(self) -> np.ndarray:
-        return np.array([math.log2(self.n), math.log2(self.slices), self.a, self.cus / self.cus_total],
-                        dtype=np.float64)
+        return features(self.n, self.slices, self.a, self.cus / self.cus_total)
 
 
 def union_keys(records) -> list:
@@ -147,13 +163,21 @@ class CUMaskedStream:
             self.handle = None
 
 
-def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, device="cuda:0",
-               repeats: int = 1, cus: int | None = None) -> TuneRecord:
-    """Times every configuration of the tuning space on one batch of
-    min(slices, batch_cap) synthetic slices (random complex samples, uniform
-    orientations: the cost depends on the geometry, not the values).  With
-    `cus` below the device's CU count the insertion runs on a CU-masked
-    stream with the library's cu_count set to match."""
+def slab_table(cfg) -> bool:
+    """The predictor's classes: slab-kernel configurations with table weights."""
+    return int(cfg.variant) == recon.RECON_VARIANT_SLAB and int(cfg.weights) == recon.RECON_WEIGHTS_TABLE
+
+
+def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = CALL_SLICES, device="cuda:0",
+               repeats: int = 3, cus: int | None = None, keep=slab_table) -> TuneRecord:
+    """Times the configurations of the tuning space that `keep` accepts on one
+    call of min(slices, batch_cap) synthetic slices (random complex samples,
+    uniform orientations: the cost depends on the geometry, not the values),
+    with the library's default batch size (so the work plan is the one it
+    runs).  Each configuration: one warm-up call, then the median of
+    `repeats` calls, each timed with events around the whole
+    recon_insert_batch.  With `cus` below the device's CU count the insertion
+    runs on a CU-masked stream with the library's cu_count set to match."""
     dev = torch.device(device)
     total = torch.cuda.get_device_properties(dev).multi_processor_count
     cus = total if cus is None else int(cus)
@@ -166,35 +190,35 @@ def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = 1500, 
     sl = torch.view_as_complex(sl).contiguous()
     q = torch.randn((count, 4), generator=g, device=dev, dtype=torch.float32)
     torch.cuda.synchronize(dev)
-    rec = recon.Reconstruction(n, device=dev, max_batch=count, blob_radius=float(np.float32(a)),
-                               stream=masked.stream if masked else None)
+    stream = masked.stream if masked else torch.cuda.current_stream(dev)
+    rec = recon.Reconstruction(n, device=dev, max_batch=max(count, CALL_SLICES), blob_radius=float(np.float32(a)),
+                               stream=stream)
     if masked:
         rec.set_config(cu_count=cus)
     default_key = config_key(recon.recon_get_config(rec.ctx))
     size = recon.recon_tune_space_size(rec.ctx)
-    ns = np.zeros(size)
-    keys = []
+    ns, keys = [], []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()       # torch creates the events on first record; the library re-records them
-    e1.record()
-    torch.cuda.synchronize()
     for i in range(size):
         cfg = recon.recon_tune_space_config(rec.ctx, i)
+        if keep is not None and not keep(cfg):
+            continue
         keys.append(config_key(cfg))
         recon.recon_set_config(rec.ctx, cfg)
-        best = float("inf")
-        for _ in range(repeats + 1):          # first run warms the configuration
-            recon.recon_set_timing_events(rec.ctx, e0, e1)
+        recon.recon_insert_batch(rec.ctx, sl, None, q, count)       # warm-up
+        t = []
+        for _ in range(repeats):
+            e0.record(stream)
             recon.recon_insert_batch(rec.ctx, sl, None, q, count)
-            recon.recon_set_timing_events(rec.ctx, None, None)
+            e1.record(stream)
             e1.synchronize()
-            best = min(best, e0.elapsed_time(e1))
-        ns[i] = best * 1e6 / count
+            t.append(e0.elapsed_time(e1))
+        ns.append(float(np.median(t)) * 1e6 / count)
     rec.close()
     if masked:
         masked.close()
-    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=ns, keys=keys, default_key=default_key, cus=cus,
-                      cus_total=total)
+    return TuneRecord(n=n, slices=slices, a=a, ns_per_slice=np.array(ns), keys=keys, default_key=default_key,
+                      cus=cus, cus_total=total)
 
 
 def soft_targets(ns: np.ndarray, temperature: float = 0.02) -> np.ndarray:
@@ -245,6 +269,11 @@ class Predictor:
             recon.recon_mlp_train_step(self.params, self.n_in, self.H, self.C, x, y, B, lr, ws, loss[i:i + 1])
         return loss.cpu().numpy().tolist()
 
+    def save(self, path: str, keys: list):
+        """Parameters, feature normalisation and class keys, in one .npz."""
+        np.savez(path, params=self.params.cpu().numpy(), mu=self.norm.mu, sd=self.norm.sd,
+                 keys=np.array(keys, dtype=np.int64), n_in=self.n_in, n_out=self.C)
+
     def predict(self, X: np.ndarray) -> np.ndarray:
         B = X.shape[0]
         x = torch.tensor(self.norm(X), dtype=torch.float32, device=self.dev)
@@ -253,6 +282,17 @@ class Predictor:
         p = torch.empty((B, self.C), dtype=torch.float32, device=self.dev)
         recon.recon_mlp_forward(self.params, self.n_in, self.H, self.C, x, B, ws, p)
         return p.cpu().numpy()
+
+
+def load_predictor(path: str, device="cuda:0"):
+    """A predictor written by Predictor.save, and its class keys."""
+    z = np.load(path)
+    model = Predictor(int(z["n_out"]), device=device, n_in=int(z["n_in"]))
+    model.params = torch.tensor(z["params"], dtype=torch.float32, device=model.dev)
+    norm = Normalizer(np.zeros((1, model.n_in)))
+    norm.mu, norm.sd = z["mu"], z["sd"]
+    model.norm = norm
+    return model, [tuple(int(v) for v in k) for k in z["keys"]]
 
 
 def regret(ns: np.ndarray, choice: np.ndarray) -> np.ndarray:
@@ -281,13 +321,16 @@ def ranked_candidates(prob: np.ndarray, runnable: np.ndarray, k: int) -> np.ndar
     return order[:min(k, int(runnable.sum()))]
 
 
-def guided_regret(ns: np.ndarray, prob: np.ndarray, k: int) -> np.ndarray:
-    """Regret of measuring the predictor's top-k runnable configurations and
-    keeping the fastest (k tuning steps)."""
+def guided_regret(ns: np.ndarray, prob: np.ndarray, k: int, default=None) -> np.ndarray:
+    """Regret of measuring the predictor's top-k runnable configurations (and
+    the default configuration default[w], when given) and keeping the
+    fastest (k or k + 1 tuning steps)."""
     out = np.zeros(ns.shape[0])
     for w in range(ns.shape[0]):
         ok = np.isfinite(ns[w])
-        cand = ranked_candidates(prob[w], ok, k)
+        cand = list(ranked_candidates(prob[w], ok, k))
+        if default is not None and default[w] >= 0 and ok[default[w]]:
+            cand.append(int(default[w]))
         out[w] = ns[w, cand].min() / ns[w, ok].min() - 1.0
     return out
 
@@ -308,12 +351,13 @@ def policy_regret(ns: np.ndarray, prob: np.ndarray, k: int, tau: float, budget: 
 
 
 def tune_with_predictor(rec, model, keys: list, features: np.ndarray, k: int = 3, tau: float = 0.05,
-                        budget: int = 10, seed: int = 0) -> dict:
+                        budget: int = 10, seed: int = 0, with_default: bool = True) -> dict:
     """Starts the library's tuner on a live reconstruction: the predictor's
-    top-k runnable configurations in rank order when it is confident, else a
-    random search of `budget` steps.  The caller then performs its
-    recon_insert_batch calls (each tuning step is real work); `judge` reads
-    the outcome afterwards."""
+    top-k runnable configurations in rank order, then the context's current
+    (default) configuration if it is not among them, when the predictor is
+    confident; else a random search of `budget` steps.  The caller then
+    performs its recon_insert_batch calls (each tuning step is real work);
+    `judge` reads the outcome afterwards."""
     size = recon.recon_tune_space_size(rec.ctx)
     space_keys = [config_key(recon.recon_tune_space_config(rec.ctx, i)) for i in range(size)]
     col = {kk: i for i, kk in enumerate(keys)}
@@ -323,6 +367,9 @@ def tune_with_predictor(rec, model, keys: list, features: np.ndarray, k: int = 3
     conf = float(p_space[runnable].max()) if runnable.any() else 0.0
     if conf >= tau:
         order = [int(i) for i in ranked_candidates(p_space, runnable, k)]
+        dkey = config_key(recon.recon_get_config(rec.ctx))
+        if with_default and dkey in space_keys and space_keys.index(dkey) not in order:
+            order.append(space_keys.index(dkey))
         recon.recon_tune_begin(rec.ctx, order=order)
         return {"policy": "predicted", "order": order, "confidence": conf}
     recon.recon_tune_begin(rec.ctx, max_steps=budget, seed=seed)
@@ -355,6 +402,8 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
     scores = np.where(np.isfinite(NSte), prob, -np.inf)    # only runnable choices
     pred = scores.argmax(axis=1)
     fin = np.where(np.isfinite(NSte), NSte, np.nan)
+    col = {k: i for i, k in enumerate(keys)}
+    dflt = np.array([col.get(r.default_key, -1) for r in test])
     out = {
         "train_workloads": len(train), "test_workloads": len(test), "configs": int(Ytr.shape[1]),
         "loss_first": losses[0], "loss_last": losses[-1],
@@ -364,7 +413,10 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
         "random_search_budget": search_budget,
         "mean_config_over_best": float((np.nanmean(fin, axis=1) / NSte.min(axis=1)).mean()),
         "regret_top3_mean": float(guided_regret(NSte, prob, 3).mean()),
+        "regret_guided_mean": float(guided_regret(NSte, prob, 3, dflt).mean()),
+        "regret_guided_max": float(guided_regret(NSte, prob, 3, dflt).max()),
         "regret_random_search3_mean": float(random_search_regret(NSte, 3, seed=seed).mean()),
+        "regret_random_search4_mean": float(random_search_regret(NSte, 4, seed=seed).mean()),
     }
     conf = np.where(np.isfinite(NSte), prob, -np.inf).max(axis=1)
     out["confidence_quartiles"] = [float(x) for x in np.quantile(conf, [0.25, 0.5, 0.75])]
@@ -374,11 +426,10 @@ def evaluate(train: list, test: list, steps: int = 3000, lr: float = 0.1, temper
         out["policy"].append({"k": 3, "tau": tau, "fallback_budget": search_budget,
                               "regret_mean": float(reg.mean()), "regret_max": float(reg.max()),
                               "steps_mean": float(st.mean()), "fallback_fraction": float(fb.mean())})
-    col = {k: i for i, k in enumerate(keys)}
-    if all(r.default_key in col and np.isfinite(NSte[w, col[r.default_key]]) for w, r in enumerate(test)):
-        d = np.array([col[r.default_key] for r in test])
-        out["regret_default_mean"] = float(regret(NSte, d).mean())
-    return out
+    if all(d >= 0 and np.isfinite(NSte[w, d]) for w, d in enumerate(dflt)):
+        out["regret_default_mean"] = float(regret(NSte, dflt).mean())
+        out["regret_default_max"] = float(regret(NSte, dflt).max())
+    return out, model, keys
 
 
 def portability_matrix(records) -> np.ndarray:
@@ -405,7 +456,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="collect tuning data, train and evaluate the learned predictor")
     ap.add_argument("--train", type=int, default=200)
     ap.add_argument("--test", type=int, default=50)
-    ap.add_argument("--batch-cap", type=int, default=1000)
+    ap.add_argument("--batch-cap", type=int, default=CALL_SLICES)
+    ap.add_argument("--repeats", type=int, default=3, help="timed calls per configuration (median)")
+    ap.add_argument("--save-model", default=None, help="write the trained predictor (.npz)")
     ap.add_argument("--n-max", type=int, default=384)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--out", default=None)
@@ -430,13 +483,16 @@ def main(argv=None):
     params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
         sample_workloads(2000, args.test, n_range=(48, args.n_max))
     for k, (n, s, a, cus) in enumerate(params):
-        records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap, cus=cus))
+        records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap, cus=cus, repeats=args.repeats))
         print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} CUs={cus} "
               f"best {records[-1].ns_per_slice.min():.1f} ns/slice ({time.time() - t0:.0f} s)",
               file=sys.stderr, flush=True)
-    res = evaluate(records[:args.train], records[args.train:], steps=args.steps)
+    res, model, keys = evaluate(records[:args.train], records[args.train:], steps=args.steps)
     res["collection_s"] = time.time() - t0
     res["batch_cap"] = args.batch_cap
+    res["repeats"] = args.repeats
+    if args.save_model:
+        model.save(args.save_model, keys)
     print(json.dumps(res), flush=True)
     if args.out:
         keys = union_keys(records)

@@ -18,4 +18,7 @@ from .phantom import (  # noqa: F401
     slices_from_projections,
     phantom_ft,
     WORKLOADS,
+    BATCHES,
+    batch_specs,
+    batch_quaternions,
 )

@@ -219,6 +219,29 @@ def make_workload(name: str = "small", n: int | None = None, S: int | None = Non
                     meta=dict(K=K, seed_phantom=sp, seed_orient=so, clustered=cl))
 
 
+# name -> (boxes, slice-count range, seed of the counts, K): several
+# reconstructions of uneven sizes inserted together; job j uses phantom seed
+# 50 + j and orientation seed 60 + j
+BATCHES = {
+    "batch8": ((64, 96, 128, 160, 192, 224, 256, 256), (2000, 20000), 5, 40),
+}
+
+
+def batch_specs(name: str = "batch8") -> list:
+    """(n, S, K, seed_phantom, seed_orient) of each job of a named batch; the
+    slice counts are drawn uniformly from the range with the batch's seed."""
+    boxes, (lo, hi), seed, K = BATCHES[name]
+    counts = np.random.default_rng(seed).integers(lo, hi + 1, size=len(boxes))
+    return [(int(n), int(S), K, 50 + j, 60 + j) for j, (n, S) in enumerate(zip(boxes, counts))]
+
+
+def batch_quaternions(spec) -> np.ndarray:
+    """The FP32 orientations make_workload draws for one job of a batch
+    (without building its slices)."""
+    n, S, K, sp, so = spec
+    return random_quaternions(np.random.default_rng(so), S).astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # 16-bit slice storage (the storage formats the library accepts)
 # --------------------------------------------------------------------------

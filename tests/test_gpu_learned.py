@@ -1,7 +1,10 @@
 """Learned configuration predictor end to end on a reduced problem: timings of
-the whole tuning space on seeded workloads, training with the library's MLP
-kernels, and the regret of the predicted configuration on held-out workloads
-against exhaustive search, the default configuration and random search."""
+the predictor's classes (slab configurations with table weights, median of
+three calls each) on seeded workloads, training with the library's MLP
+kernels, and on held-out workloads the regret of the guided search (the
+predicted top 3 and the default configuration, measured) against exhaustive
+search, against the default configuration alone and against a random search
+of the same number of steps."""
 import numpy as np
 import pytest
 
@@ -24,23 +27,25 @@ def test_learned_predictor_end_to_end(env):
     recs = []
     for k, (n, s, a, cus) in enumerate(train_p + test_p):
         print(f"[gpu] learned timing workload {k} n={n} S={s} a={a:.2f} CUs={cus}", flush=True)
-        recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=1, cus=cus))
+        recs.append(learned.time_space(n, s, a, seed=k, batch_cap=300, repeats=3, cus=cus))
     for r in recs:
         assert len(r.keys) == r.ns_per_slice.size and np.all(r.ns_per_slice > 0)
         assert r.default_key in r.keys                 # the default is a member of the space
     keys = learned.union_keys(recs)
     ns = learned.time_matrix(recs, keys)
     assert np.all(np.isfinite(ns.min(axis=1)))
-    res = learned.evaluate(recs[:14], recs[14:], steps=1500)
+    res, _, _ = learned.evaluate(recs[:14], recs[14:], steps=1500)
     print("   ", res, flush=True)
     assert res["loss_last"] < res["loss_first"]
-    # picking by prediction costs no tuning steps and lands far closer to the
-    # best than an average configuration (the comparison with the tuned
-    # default needs the full-size evaluation: on 6 workloads timed over a few
-    # tens of microseconds it is within timing noise)
     assert np.isfinite(res["regret_learned_mean"]) and res["regret_learned_mean"] >= 0.0
+    # the single prediction lands far closer to the best than an average configuration
     assert res["regret_learned_mean"] < 0.5 * (res["mean_config_over_best"] - 1.0)
     assert res["regret_top3_mean"] <= res["regret_learned_mean"] + 1e-12     # top-3 contains top-1
+    # the guided search measures the default too, so it is never worse than
+    # running the default, and it beats a random search of its step budget
+    assert res["regret_guided_mean"] <= res["regret_default_mean"] + 1e-12
+    assert res["regret_guided_mean"] <= res["regret_top3_mean"] + 1e-12
+    assert res["regret_guided_mean"] < res["regret_random_search4_mean"]
     assert all(0.0 <= pol["fallback_fraction"] <= 1.0 for pol in res["policy"])
 
     # live: the tuner measures the predictor's candidates on real insertions
@@ -51,16 +56,19 @@ def test_learned_predictor_end_to_end(env):
     r = recs[14]
     rec = recon.Reconstruction(r.n, device=torch.device("cuda:0"), max_batch=200,
                                blob_radius=float(np.float32(r.a)))
+    default = learned.config_key(recon.recon_get_config(rec.ctx))
     plan = learned.tune_with_predictor(rec, model, keys_u, r.features(), k=3, tau=0.0)
-    assert plan["policy"] == "predicted" and len(plan["order"]) == 3
+    assert plan["policy"] == "predicted" and len(plan["order"]) in (3, 4)
+    space = [learned.config_key(recon.recon_tune_space_config(rec.ctx, i)) for i in plan["order"]]
+    assert default in space                      # the default is always measured
     sl = torch.zeros((200, r.n, r.n // 2 + 1), dtype=torch.complex64, device="cuda:0")
     q = torch.tensor([[1.0, 0.0, 0.0, 0.0]] * 200, dtype=torch.float32, device="cuda:0")
-    for _ in range(3):
+    for _ in range(len(plan["order"])):
         recon.recon_insert_batch(rec.ctx, sl, None, q, 200)
     recon.recon_tune_end(rec.ctx)
     out = learned.judge(rec, plan)
     print("   live:", out, flush=True)
-    assert out["steps"] == 3 and out["best_index"] in plan["order"] and not out["active"]
+    assert out["steps"] == len(plan["order"]) and out["best_index"] in plan["order"] and not out["active"]
     rec.close()
     rec = recon.Reconstruction(r.n, device=torch.device("cuda:0"), blob_radius=float(np.float32(r.a)))
     plan = learned.tune_with_predictor(rec, model, keys_u, r.features(), tau=1.1)   # never confident

@@ -82,3 +82,20 @@ def test_portability_matrix():
     assert m[0, 1] == 0.5                 # a's best on b: 2 / 4
     assert m[1, 0] == 0.5                 # b's best on a: 1 / 2
     assert np.isnan(m[0, 2]) and m[1, 2] == 1.0
+
+
+def test_guided_search_with_the_default_is_never_worse_than_the_default():
+    ns = np.array([[1.0, 1.2, 1.5, 2.0, 1.1], [2.0, 1.0, 3.0, 1.5, 4.0]])
+    prob = np.array([[0.1, 0.2, 0.3, 0.35, 0.05], [0.5, 0.1, 0.2, 0.15, 0.05]])
+    dflt = np.array([4, 1])
+    g3 = learned.guided_regret(ns, prob, 3)
+    gd = learned.guided_regret(ns, prob, 3, dflt)
+    d = learned.regret(ns, dflt)
+    assert np.all(gd <= g3 + 1e-15) and np.all(gd <= d + 1e-15)
+    assert gd[1] == 0.0 and g3[1] > 0.0         # the default was the best and not predicted
+
+
+def test_features_count_slices_per_call():
+    f = learned.features(128, 50000, 1.9, 0.5)
+    assert f[0] == 7.0 and f[1] == pytest.approx(np.log2(1500)) and f[2] == 1.9 and f[3] == 0.5
+    assert learned.features(128, 1000, 1.9, 1.0)[1] == pytest.approx(np.log2(1000))
