@@ -459,6 +459,8 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     std::vector<double> coef;
     c->g.nterms = blob_coefficients(p->blob_alpha, p->blob_order, &coef);   // > 0 if table_size == 0 (validated)
     const int mode = weight_source(*p, RECON_WEIGHTS_DEFAULT);
+    // the current configuration names its weight source, as the tuning space does
+    c->cfg.weights = mode == recon::WEIGHT_OTF ? RECON_WEIGHTS_OTF : RECON_WEIGHTS_TABLE;
     if (mode == recon::WEIGHT_OTF) c->cfg.slab_flags = 4;   // no window preload on the fly
     if (slab_wide_ok(c->g, mode, c->max_lds)) {
         // three waves per SIMD where the 11-wave instance applies (the

@@ -59,3 +59,46 @@ def cutoff_flips(W, Wo, edge: float):
     noise = 1e-5 * np.abs(Wo)
     k = np.rint(dW / edge)
     return (k >= 1) & (dW > 0.5 * edge + noise) & (np.abs(dW - k * edge) <= 0.01 * edge + noise)
+
+
+def flip_limit(U: int, n: int, a: float) -> float:
+    """Most cut-off flips consistent with FP32 geometry, for U pairs in a box n.
+
+    A voxel position relative to a rotated sample carries an FP32 error of a
+    few units in the last place of the largest coordinate h = n/2 (taken as 8
+    ulp), so d^2 near a^2 is uncertain by delta = 2 a * 8 h 2^-23.  With the
+    pair offsets spread uniformly over the blob's ball, P(d^2 <= x) =
+    (x / a^2)^(3/2), so a share of about 3 delta / a^2 of the pairs lies within
+    delta of the cut-off; each flipped voxel needs at least one such pair.
+    The limit is four times that expectation (and at least one voxel)."""
+    delta = 2.0 * a * 8.0 * max(n // 2, 1) * 2.0 ** -23
+    return max(1.0, 4.0 * 3.0 * delta / (a * a) * U)
+
+
+def progress(request, msg: str) -> None:
+    """Prints past pytest's output capture, so a long CPU step (the oracle
+    over a large workload) reports as it goes."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    if capman is None:
+        print(msg, flush=True)
+        return
+    with capman.global_and_fixture_disabled():
+        print(msg, flush=True)
+
+
+def oracle_insert_chunked(request, n, slices, quats, chunk=2500, **kw):
+    """oracle.insert over the slices in chunks, summed (G and W are sums over
+    slices), with a progress line per chunk."""
+    G = W = None
+    U = 0
+    S = len(quats)
+    for s0 in range(0, S, chunk):
+        g, w, u = oracle.insert(n, slices[s0:s0 + chunk], quats[s0:s0 + chunk], **kw)
+        if G is None:
+            G, W = g, w
+        else:
+            G += g
+            W += w
+        U += u
+        progress(request, f"[cpu] oracle: {min(s0 + chunk, S)} of {S} slices")
+    return G, W, U

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import errors, fmt as fmt_errors
+from parity_util import errors, fmt as fmt_errors, oracle_insert_chunked, progress
 from synth.phantom import dequantize_slices, quantize_slices
 
 pytestmark = pytest.mark.gpu
@@ -35,15 +35,17 @@ def env():
 
 
 @pytest.fixture(scope="module")
-def workload():
-    print("[gpu] generating the n=256, 50,000-slice workload", flush=True)
-    return synth.make_workload("precision")
+def workload(request):
+    progress(request, "[cpu] generating the n=256, 50,000-slice workload")
+    w = synth.make_workload("precision")
+    progress(request, "[cpu] workload generated")
+    return w
 
 
 @pytest.fixture(scope="module")
-def oracle_whole(workload):
-    print("[cpu] FP64 oracle over the 50,000 complex64 slices (16 threads)", flush=True)
-    G, W, _ = oracle.insert(workload.n, workload.slices, workload.quats, nthreads=16)
+def oracle_whole(request, workload):
+    progress(request, "[cpu] FP64 oracle over the 50,000 complex64 slices (16 threads)")
+    G, W, _ = oracle_insert_chunked(request, workload.n, workload.slices, workload.quats, nthreads=16)
     return G, W, oracle.finalize(G, W)
 
 

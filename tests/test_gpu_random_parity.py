@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import cutoff_flips, errors, fmt
+from parity_util import cutoff_flips, errors, flip_limit, fmt
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -74,12 +74,12 @@ def test_random_case(env, case):
         assert not G.any() and not W.any()
         return
     blob = oracle.Blob(a=a, alpha=alpha, m=m)
-    Go, Wo, _ = oracle.insert(n, slices[keep], quats[keep], blob=blob, r_max=r_max)
+    Go, Wo, U = oracle.insert(n, slices[keep], quats[keep], blob=blob, r_max=r_max)
     Vo = oracle.finalize(Go, Wo)
     flip = cutoff_flips(W, Wo, blob.table()[-1])
     reached = int((Wo > 0).sum())
     print(f"   b(a^2) = {blob.table()[-1]:.3g}: {int(flip.sum())} cut-off flips of {reached} voxels", flush=True)
-    assert flip.sum() <= max(1, 1e-4 * reached)
+    assert flip.sum() <= flip_limit(U, n, blob.a)
     k = ~flip
     e = errors(G[k], W[k], Vg[k], Go[k], Wo[k], Vo[k])
     print("   " + fmt(e), flush=True)

@@ -28,7 +28,7 @@ def test_tuning_space_is_runnable(env):
     for i in range(n):
         c = recon.recon_tune_space_config(rec.ctx, i)
         recon.recon_set_config(rec.ctx, c)      # every member is accepted
-        seen.add((c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags))
+        seen.add((c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags, c.weights))
     assert len(seen) == n
     with pytest.raises(recon.ReconError):
         recon.recon_tune_space_config(rec.ctx, n)
