@@ -144,6 +144,27 @@ recon_status recon_query_sizes(const recon_params *p, size_t *g_bytes, size_t *w
 recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
                         size_t ws_bytes, void *stream, recon_ctx **out);
 
+/* recon_init without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a static device array
+ * of the library, RECON_STATIC_WS_BYTES (192 MiB) on each device it runs on,
+ * held until the process ends.  The call allocates no device memory; the
+ * caller still passes G and W as for recon_init.  Every later call on the
+ * context uses that array exactly as recon_init's contexts use d_ws, with the
+ * same kernels and results.
+ *
+ * One context per device may hold the array at a time: a second
+ * recon_init_static on a device whose array belongs to a live context fails
+ * with RECON_EINVAL; recon_destroy releases it.  The array keeps the last
+ * context's contents; recon_init_static clears what must start at zero (the
+ * counters) and rewrites the table and the work plan.  Calls on the context
+ * that overlap (other threads or streams) race, as on any context.
+ * Parameters whose workspace (recon_query_sizes) exceeds the array fail with
+ * RECON_ENOMEM before any device call; the library's defaults fit every box
+ * up to n = 1024.  Otherwise the errors of recon_init. */
+#define RECON_STATIC_WS_BYTES ((size_t)192 << 20)
+recon_status recon_init_static(const recon_params *p, void *d_G, void *d_W, void *stream, recon_ctx **out);
+
 /* Zeroes G and W again and clears the slice counters (asynchronous). */
 recon_status recon_reset(recon_ctx *ctx);
 

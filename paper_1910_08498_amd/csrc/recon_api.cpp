@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -334,12 +335,65 @@ struct recon_ctx {
     hipEvent_t ev_start;  // optional timing events around the insertion kernel
     hipEvent_t ev_stop;
     TuneState tune;
+    int static_device = -1;   // >= 0: ws is that device's static workspace (recon_init_static)
 };
 
 // exact-geometry axis remainders: after the max_batch orientation records
 static float4 *orient_rem(recon_ctx *c)
 {
     return reinterpret_cast<float4 *>(c->ws + c->L.orient + static_cast<size_t>(c->p.max_batch) * sizeof(Orient));
+}
+
+// ---------------------------------------------------------------------------
+// static workspace (recon_init_static): the workspace of one context per
+// device in a device array of the library's own, for callers that cannot
+// allocate device memory.  In host code `scratch` only names the symbol; its
+// device address comes from hipGetSymbolAddress, resolved once per device
+// with that device current, and only that address is handed to kernels and
+// copies.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticWsBytes = RECON_STATIC_WS_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticWs {
+    unsigned char *ptr = nullptr;   // device address of `scratch` on this device (nullptr: not resolved)
+    bool in_use = false;            // a live context holds it
+};
+std::mutex g_static_mu;
+StaticWs g_static_ws[kMaxDevices];
+}  // namespace
+
+// Resolves the current device's static workspace and marks it in use.
+static recon_status acquire_static_workspace(int *dev, unsigned char **ws)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (*dev < 0 || *dev >= kMaxDevices) return fail(RECON_EDEVICE, "device %d beyond the static table", *dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticWs &s = g_static_ws[*dev];
+    if (s.in_use)
+        return fail(RECON_EINVAL, "the static workspace of device %d belongs to a live context: destroy it first",
+                    *dev);
+    if (!s.ptr) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static workspace)");
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+            return fail(RECON_EDEVICE, "static workspace address is NULL or not 256-byte aligned");
+        s.ptr = static_cast<unsigned char *>(ptr);
+    }
+    s.in_use = true;
+    *ws = s.ptr;
+    return RECON_OK;
+}
+
+static void release_static_workspace(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_ws[dev].in_use = false;
 }
 
 static recon_status tune_collect(recon_ctx *c);
@@ -1150,7 +1204,34 @@ void recon_destroy(recon_ctx *c)
 {
     if (!c) return;
     tune_release(c);
+    release_static_workspace(c->static_device);
     delete c;
+}
+
+recon_status recon_init_static(const recon_params *p, void *d_G, void *d_W, void *stream, recon_ctx **out)
+{
+    if (!out) return fail(RECON_EINVAL, "out is NULL");
+    *out = nullptr;
+    recon_status st = validate(p);
+    if (st != RECON_OK) return st;
+    // the size check comes before any device call
+    size_t need = 0;
+    recon_query_sizes(p, nullptr, nullptr, &need);
+    if (need > kStaticWsBytes)
+        return fail(RECON_ENOMEM, "these parameters need %zu bytes of workspace; the static workspace holds %zu "
+                                  "(use recon_init with a caller buffer, or a smaller max_batch)",
+                    need, kStaticWsBytes);
+    int dev = -1;
+    unsigned char *ws = nullptr;
+    st = acquire_static_workspace(&dev, &ws);
+    if (st != RECON_OK) return st;
+    st = recon_init(p, d_G, d_W, ws, kStaticWsBytes, stream, out);
+    if (st != RECON_OK) {
+        release_static_workspace(dev);
+        return st;
+    }
+    (*out)->static_device = dev;
+    return RECON_OK;
 }
 
 }  // extern "C"

@@ -72,6 +72,7 @@ def load_library():
         "recon_default_params": ([i32, P(recon_params)], i32),
         "recon_query_sizes": ([P(recon_params), P(sz), P(sz), P(sz)], i32),
         "recon_init": ([P(recon_params), vp, vp, vp, sz, vp, P(vp)], i32),
+        "recon_init_static": ([P(recon_params), vp, vp, vp, P(vp)], i32),
         "recon_reset": ([vp], i32),
         "recon_insert_batch": ([vp, vp, vp, vp, i32], i32),
         "recon_finalize": ([vp, vp, ctypes.c_float], i32),
@@ -140,6 +141,12 @@ def recon_init(p: recon_params, G, W, ws, stream=None):
     ctx = ctypes.c_void_p()
     _check(load_library().recon_init(ctypes.byref(p), _ptr(G), _ptr(W), _ptr(ws), ws.numel() * ws.element_size(),
                                      _stream(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def recon_init_static(p: recon_params, G, W, stream=None):
+    ctx = ctypes.c_void_p()
+    _check(load_library().recon_init_static(ctypes.byref(p), _ptr(G), _ptr(W), _stream(stream), ctypes.byref(ctx)))
     return ctx
 
 
@@ -293,9 +300,11 @@ class Reconstruction:
     """Owns G, W and the workspace as torch tensors on `device` and a context.
 
     insert() hands slices and quaternions (device tensors) to the library in
-    chunks of at most max_batch; finalize() returns V as a complex64 tensor."""
+    chunks of at most max_batch; finalize() returns V as a complex64 tensor.
+    static_workspace=True takes the library's static workspace
+    (recon_init_static) instead of allocating one."""
 
-    def __init__(self, n: int, device="cuda", stream=None, **overrides):
+    def __init__(self, n: int, device="cuda", stream=None, static_workspace=False, **overrides):
         load_library()
         self.params = recon_default_params(n)
         for k, v in overrides.items():
@@ -305,10 +314,14 @@ class Reconstruction:
         self.device = torch.device(device)
         self.G = torch.empty((dim, dim, dim), dtype=torch.complex64, device=self.device)
         self.W = torch.empty((dim, dim, dim), dtype=torch.float32, device=self.device)
-        self.ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
         assert self.G.numel() * 8 == gb and self.W.numel() * 4 == wb
         self.stream = stream
-        self.ctx = recon_init(self.params, self.G, self.W, self.ws, stream)
+        if static_workspace:
+            self.ws = None
+            self.ctx = recon_init_static(self.params, self.G, self.W, stream)
+        else:
+            self.ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
+            self.ctx = recon_init(self.params, self.G, self.W, self.ws, stream)
         self._keep = []
 
     @property

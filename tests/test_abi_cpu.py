@@ -132,3 +132,20 @@ int main(void) {
             ctypes.sizeof(recon.recon_tune_opts), recon.recon_tune_opts.order_count.offset,
             recon.recon_tune_opts.order.offset, ctypes.sizeof(recon.recon_tune_info)]
     assert got == want
+
+
+def test_static_workspace_rejects_oversized_parameters_before_any_device_call(recon):
+    # 2^24 slices per call need ~2.9 GB of orientation records, beyond the
+    # static workspace; the size check precedes every device call, so it
+    # answers here without a GPU
+    p = recon.recon_default_params(128)
+    p.max_batch = 1 << 24
+    assert recon.recon_query_sizes(p)[2] > (192 << 20)
+    lib = recon.load_library()
+    ctx = ctypes.c_void_p()
+    rc = lib.recon_init_static(ctypes.byref(p), None, None, None, ctypes.byref(ctx))
+    assert rc == recon.RECON_ENOMEM and not ctx.value
+    assert "static workspace" in lib.recon_last_error().decode()
+    # the library's defaults fit every box up to n = 1024
+    for n in (64, 128, 256, 512, 1024):
+        assert recon.recon_query_sizes(recon.recon_default_params(n))[2] <= (192 << 20)
