@@ -152,10 +152,16 @@ struct Plan {
 // Tiles of E x E x E voxels (E = 4 or 8) over the half box x in [0, h],
 // y, z in [-h, h].  A tile at centre distance r sees, for uniformly
 // distributed slice normals, about min(1, (a + ext) / r) of the slices
-// (ext = half the tile diagonal); tiles whose every voxel is out of reach of
-// the disk |k| < r_max are dropped.  Heavy tiles are split into up to `split`
-// slice ranges so that no item costs much more than `target` slice visits;
-// items are ordered by decreasing estimated cost.
+// (ext = half the tile diagonal); its cost is that share of the slice visits,
+// scaled by the part of its voxels inside the box and inside the reach
+// sphere |v| < r_max + a (sampled on a 3 x 3 x 3 grid); tiles whose every
+// voxel is out of reach are dropped.  Tiles are split into up to `split`
+// slice ranges: the persistent waves pull items largest first, so the items
+// that start last set the tail of the launch.  The costliest tiles, holding
+// the first 40 % of the cost, are cut into items of twice the target cost,
+// the next 40 % into items of the target, and the cheapest 20 %, which run
+// last, into items of a quarter of it.  Items are ordered by decreasing
+// estimated cost.
 Plan make_plan(const recon_params &p, int split, int E)
 {
     Plan plan;
@@ -180,23 +186,40 @@ Plan make_plan(const recon_params &p, int split, int E)
                 const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1), cz = 0.5 * (z0 + z1);
                 const double r = std::sqrt(cx * cx + cy * cy + cz * cz);
                 const double vol = (x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1) / (E * E * E);
+                int in = 0;
+                for (int k = 0; k < 27; ++k) {
+                    const double sx = x0 + 0.5 * (k % 3) * (x1 - x0), sy = y0 + 0.5 * ((k / 3) % 3) * (y1 - y0),
+                                 sz = z0 + 0.5 * (k / 9) * (z1 - z0);
+                    in += sx * sx + sy * sy + sz * sz < R * R ? 1 : 0;
+                }
                 const double frac = std::min(1.0, (a + ext) / std::max(r, 1e-9));
-                const double cost = frac * p.max_batch * (E == 8 ? std::max(vol, 0.25) : 1.0);
+                const double share = vol * std::max(in, 1) / 27.0;
+                const double cost = frac * p.max_batch * (E == 8 ? std::max(share, 0.25) : 1.0);
                 tiles.push_back({tx + TX * (ty + TY * tz), cost});
                 total += cost;
             }
     // target item cost: an eighth of the mean cost per wavefront slot of a
-    // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits:
-    // the persistent waves pull items largest first, and small items keep the
-    // tail of the launch short (a quarter measured 5 % slower)
+    // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits
     const double slots = 256.0 * (E == 4 ? 16.0 : 8.0);
     const double target = std::max(24.0, total / (slots * 8.0));
+    std::vector<int> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x].cost > tiles[y].cost; });
+    std::vector<int> np_of(tiles.size());
+    double cum = 0.0;
+    for (int i : order) {
+        const double at = cum / std::max(total, 1e-30);
+        const double t = at < 0.4 ? 2.0 * target : (at < 0.8 ? target : std::max(6.0, 0.25 * target));
+        cum += tiles[i].cost;
+        int np = static_cast<int>(std::ceil(tiles[i].cost / t));
+        np = std::max(1, std::min(np, split));
+        np_of[i] = std::min(np, std::max(1, p.max_batch));
+    }
     struct Tmp { Item it; double cost; };
     std::vector<Tmp> tmp;
-    for (const Est &e : tiles) {
-        int np = static_cast<int>(std::ceil(e.cost / target));
-        np = std::max(1, std::min(np, split));
-        np = std::min(np, std::max(1, p.max_batch));
+    for (size_t i = 0; i < tiles.size(); ++i) {
+        const Est &e = tiles[i];
+        const int np = np_of[i];
         const int slot = np > 1 ? plan.nslots : -1;
         if (np > 1) plan.nslots += np;
         for (int k = 0; k < np; ++k) tmp.push_back({{e.tile, k, np, np > 1 ? slot + k : -1}, e.cost / np});
@@ -243,7 +266,9 @@ Layout worst_layout(const recon_params &p)
 {
     Plan p4 = make_plan(p, kMaxSplit, 4), p8 = make_plan(p, kMaxSplit, 8);
     const int nitems = static_cast<int>(std::max(p4.items.size(), p8.items.size()));
-    const size_t pv = std::max(static_cast<size_t>(p4.nslots) * 64, static_cast<size_t>(p8.nslots) * 512);
+    // partial sums per split-tile slot: a float4 per voxel for the binned
+    // kernel (64 voxels), three planes of 512 floats for the slab kernel
+    const size_t pv = std::max(static_cast<size_t>(p4.nslots) * 64, static_cast<size_t>(p8.nslots) * 384);
     return layout_for(p, nitems, pv);
 }
 

@@ -164,10 +164,10 @@ __device__ __forceinline__ int sel3i(int i, int x, int y, int z)
 // products and uxl, uyl the remainders' products, added once the large parts
 // have cancelled (else uxl, uyl are unused).  MODE: the weight source (tab
 // holds the table, or on the fly the polynomial's coefficients).
-template <int WIN, bool RIM, int MODE, bool PRELOAD, bool EXACT>
+template <int WIN, int ROWS, bool RIM, int MODE, bool PRELOAD, bool EXACT>
 __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, const float *__restrict__ tab,
                                            const Geom &g, float uxs, float uxl, float uys, float uyl, float uzs,
-                                           float s, float inv_s, int kx_lo, int ky_lo, float &pr, float &pi,
+                                           float s, float inv_s, int kx_lo, int ky_lo, int j0, float &pr, float &pi,
                                            float &pw)
 {
     constexpr int RECT = SlabShape<WIN>::RECT;
@@ -178,8 +178,9 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
     const float fy0 = ceilf(fmaf(EXACT ? uys + uyl : uys, inv_s, -g.a));
     // the staged rectangle holds every window; the clamp only guards the buffer
     const int off = min(max(__mul24(static_cast<int>(fy0) - ky_lo, RECT) + (static_cast<int>(fx0) - kx_lo), 0), MAXOFF);
-    const float2 *base = rect + off;
-    float dxs[WIN], dys[WIN];
+    // rows j0 .. j0 + ROWS - 1 of the window (all of them when ROWS == WIN)
+    const float2 *base = rect + off + (ROWS == WIN ? 0 : __mul24(j0, RECT));
+    float dxs[WIN], dys[ROWS];
     float dx0 = fmaf(-s, fx0, uxs), dy0 = fmaf(-s, fy0, uys);
     if constexpr (EXACT) {
         // uxs and s fx0 are exact, so the fma rounds once at the size of the
@@ -192,18 +193,26 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
     for (int i = 0; i < WIN; ++i) {
         const float dx = i == 0 ? dx0 : fmaf(-s, static_cast<float>(i), dx0);
         dxs[i] = dx * dx;
-        const float dy = i == 0 ? dy0 : fmaf(-s, static_cast<float>(i), dy0);
-        dys[i] = fmaf(dy, dy, uz2);
+    }
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+        const float dy = ROWS == WIN ? (j == 0 ? dy0 : fmaf(-s, static_cast<float>(j), dy0))
+                                     : fmaf(-s, static_cast<float>(j0 + j), dy0);
+        dys[j] = fmaf(dy, dy, uz2);
     }
     // rim gate per cell: kx^2 < r_max^2 - ky^2 (integers below 2^24: exact,
     // so the same test as kx^2 + ky^2 < r_max^2), per column and per row
-    float kx2[WIN], rem[WIN];
+    float kx2[WIN], rem[ROWS];
     if (RIM) {
 #pragma unroll
         for (int i = 0; i < WIN; ++i) {
-            const float kx = fx0 + static_cast<float>(i), ky = fy0 + static_cast<float>(i);
+            const float kx = fx0 + static_cast<float>(i);
             kx2[i] = kx * kx;
-            rem[i] = fmaf(-ky, ky, g.r2max);
+        }
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const float ky = fy0 + static_cast<float>(ROWS == WIN ? j : j0 + j);
+            rem[j] = fmaf(-ky, ky, g.r2max);
         }
     }
     float sr = 0.f, si = 0.f, sw = 0.f;
@@ -212,9 +221,9 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         // below and must not feed large powers into Horner's rule), then the
         // polynomial for all cells at once, four coefficients per LDS read
         // (the same address in every lane)
-        float sv[WIN * WIN], acc[WIN * WIN];
+        float sv[ROWS * WIN], acc[ROWS * WIN];
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) {
                 sv[j * WIN + i] = fmaxf(1.0f - (dxs[i] + dys[j]), 0.f);
@@ -223,16 +232,16 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
         for (int c = g.nterms - 4; c >= 0; c -= 4) {
             const float4 k4 = *reinterpret_cast<const float4 *>(tab + c);
 #pragma unroll
-            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.w);
+            for (int k = 0; k < ROWS * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.w);
 #pragma unroll
-            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.z);
+            for (int k = 0; k < ROWS * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.z);
 #pragma unroll
-            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.y);
+            for (int k = 0; k < ROWS * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.y);
 #pragma unroll
-            for (int k = 0; k < WIN * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.x);
+            for (int k = 0; k < ROWS * WIN; ++k) acc[k] = fmaf(acc[k], sv[k], k4.x);
         }
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) {
                 const int k = j * WIN + i;
@@ -266,28 +275,28 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
     };
     if (PRELOAD) {
         // every LDS read of the window is issued before any is consumed
-        float t[WIN * WIN];
-        unsigned idx[WIN * WIN];
+        float t[ROWS * WIN];
+        unsigned idx[ROWS * WIN];
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) {
                 t[j * WIN + i] = dxs[i] + dys[j];
                 idx[j * WIN + i] = min(static_cast<unsigned>(t[j * WIN + i]), static_cast<unsigned>(g.N));
             }
-        float t0[WIN * WIN], t1[WIN * WIN];
-        float2 fv[WIN * WIN];
+        float t0[ROWS * WIN], t1[ROWS * WIN];
+        float2 fv[ROWS * WIN];
 #pragma unroll
-        for (int k = 0; k < WIN * WIN; ++k) {
+        for (int k = 0; k < ROWS * WIN; ++k) {
             t0[k] = tab[idx[k]];
             t1[k] = LERP ? tab[idx[k] + 1] : 0.f;
         }
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) fv[j * WIN + i] = base[j * RECT + i];
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) {
                 const int k = j * WIN + i;
@@ -298,7 +307,7 @@ __device__ __forceinline__ void window_lds(const float2 *__restrict__ rect, cons
             }
     } else {
 #pragma unroll
-        for (int j = 0; j < WIN; ++j)
+        for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int i = 0; i < WIN; ++i) {
                 const float tk = dxs[i] + dys[j];
@@ -453,6 +462,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 float4 b1, b2, b3;           // remainders of the scaled axes (exact geometry)
                 int kx_lo, ky_lo, wx, wy;    // staged rectangle: columns kx_lo.., rows ky_lo..
                 int rim;                     // int, not bool: no padding bytes in the struct copies
+                int fast;                    // staging: 1 all direct, -1 all mirrored (inside the disk), 0 mixed
                 int H;                       // hits
                 int nq;                      // loads per lane
                 float scale;
@@ -461,7 +471,18 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             // complex64 value, or the packed 16-bit pair in .x.  Decoding waits
             // for the loads, so it happens at commit.
             float2 cell[NC];
-            int dst[NC];
+            int neg[NC];      // mixed staging: the sample is mirrored (conjugated at commit)
+            // Staged cells: rows of RECT cells, cell c = 64 q + lane of load q at
+            // row c / RECT, column c % RECT, so its LDS slot is c itself.  Its
+            // offset within the slice relative to the rectangle's first sample
+            // (row stride sw) is a constant of the item.
+            constexpr int eb = DT == 0 ? 8 : 4;
+            int loff[NC];
+#pragma unroll
+            for (int qq = 0; qq < NC; ++qq) {
+                const int c = qq * 64 + lane;
+                loff[qq] = (__mul24(c / RECT, g.sw) + c % RECT) * eb;
+            }
 
             auto setup = [&](int s, Stage &st) {
                 // s is wave-uniform: the orientation and scale are read with scalar
@@ -554,45 +575,55 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const int fxm = max(abs(st.kx_lo), abs(st.kx_lo + st.wx - 1));
                 const int fym = max(abs(st.ky_lo), abs(st.ky_lo + st.wy - 1));
                 st.rim = static_cast<float>(fxm * fxm + fym * fym) < g.r2max ? 0 : 1;
-                st.nq = (st.wx * st.wy + 63) >> 6;
+                // inside the disk and on one side of kx = 0: every sample comes
+                // from one run of rows, directly (kx >= 1) or mirrored (kx <= -1)
+                st.fast = st.rim ? 0 : (st.kx_lo >= 1 ? 1 : (st.kx_lo + st.wx <= 0 ? -1 : 0));
+                st.nq = (RECT * st.wy + 63) >> 6;
                 return H;
             };
 
-            // (2) loads of the staged rectangle, Hermitian rule and disk applied
+            // (2) loads of the staged rows, Hermitian rule and disk applied
             auto issue = [&](int s, const Stage &st) {
-                const int wx = st.wx;
-                const int ncell = wx * st.wy;
-                // (c + 1/2) / wx stays at least 1 / (2 wx) away from an integer, far
-                // above the hardware reciprocal's error
-                const float inv_wx = __builtin_amdgcn_rcpf(static_cast<float>(wx));
                 // buffer resource over this slice: 32-bit offsets, hardware bounds check
                 // (reads at or past the record size return zero: cells outside
                 // the disk are loaded from there and so stage as zero)
-                constexpr int eb = DT == 0 ? 8 : 4;
                 const int bytes = static_cast<int>(slen * eb);
                 const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<unsigned char *>(static_cast<const unsigned char *>(slices) +
                                                 static_cast<size_t>(s) * slen * eb),
                     static_cast<short>(0), bytes, 0x00020000);
                 int off[NC];
+                if (st.fast != 0) {
+                    // one run of rows: direct samples at row ky + h, column kx;
+                    // mirrored ones at row h - ky, column -kx, i.e. the same
+                    // offsets counted backwards from the first sample's mirror.
+                    // Cells right of the rectangle may wrap into the next stored
+                    // row and cells below it may fall past the slice (zero); no
+                    // window reads them.
+                    const int base = st.fast > 0 ? (__mul24(st.ky_lo + g.h, g.sw) + st.kx_lo) * eb
+                                                 : (__mul24(g.h - st.ky_lo, g.sw) - st.kx_lo) * eb;
     #pragma unroll
-                for (int qq = 0; qq < NC; ++qq) {
-                    if (qq >= st.nq) break;
-                    const int c = qq * 64 + lane;
-                    const int cy_ = static_cast<int>((static_cast<float>(c) + 0.5f) * inv_wx);
-                    const int cx_ = c - cy_ * wx;
-                    const int kx = st.kx_lo + cx_, ky = st.ky_lo + cy_;
-                    // (operands below 2^11: 24-bit multiplies run at full rate)
-                    const bool valid = c < ncell && static_cast<float>(__mul24(kx, kx) + __mul24(ky, ky)) < g.r2max;
-                    const bool direct = kx > 0 || (kx == 0 && ky >= 0);
-                    const int row = direct ? ky + g.h : g.h - ky;
-                    const int col = direct ? kx : -kx;
-                    off[qq] = valid ? (__mul24(row, g.sw) + col) * eb : bytes;
-                    // the sign flip of mirrored samples is applied at commit
-                    dst[qq] = c < ncell ? (direct ? 1 : -1) * (__mul24(cy_, RECT) + cx_ + 1) : 0;
+                    for (int qq = 0; qq < NC; ++qq) off[qq] = st.fast > 0 ? base + loff[qq] : base - loff[qq];
+                } else {
+    #pragma unroll
+                    for (int qq = 0; qq < NC; ++qq) {
+                        if (qq >= st.nq) break;
+                        const int c = qq * 64 + lane;
+                        const int cy_ = c / RECT, cx_ = c % RECT;
+                        const int kx = st.kx_lo + cx_, ky = st.ky_lo + cy_;
+                        // (operands below 2^11: 24-bit multiplies run at full rate)
+                        const bool valid = cx_ < st.wx && cy_ < st.wy &&
+                                           static_cast<float>(__mul24(kx, kx) + __mul24(ky, ky)) < g.r2max;
+                        const bool direct = kx > 0 || (kx == 0 && ky >= 0);
+                        const int row = direct ? ky + g.h : g.h - ky;
+                        const int col = direct ? kx : -kx;
+                        off[qq] = valid ? (__mul24(row, g.sw) + col) * eb : bytes;
+                        // the sign flip of mirrored samples is applied at commit
+                        neg[qq] = direct ? 0 : 1;
+                    }
                 }
-                // all loads back to back; only as many as the rectangle needs
-                // (st.nq is wave-uniform)
+                // all loads back to back; only as many as the rectangle's rows
+                // need (st.nq is wave-uniform)
                 if constexpr (DT == 0) {
     #pragma unroll
                     for (int qq = 0; qq < NC; ++qq)
@@ -607,11 +638,13 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 }
             };
 
-            // (3) decode and write the staged samples to LDS
+            // (3) decode and write the staged samples to LDS (cell c to slot c;
+            // the last load's lanes past the rectangle write nothing)
             auto commit = [&](const Stage &st) {
     #pragma unroll
                 for (int qq = 0; qq < NC; ++qq) {
-                    if (qq < st.nq && dst[qq] != 0) {
+                    const int c = qq * 64 + lane;
+                    if (qq < st.nq && (qq < NC - 1 || c < RECT2)) {
                         float2 v;
                         if constexpr (DT == 0) {
                             v = cell[qq];
@@ -625,8 +658,8 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                                 v = make_float2(__uint_as_float(raw << 16), __uint_as_float(raw & 0xffff0000u));
                             }
                         }
-                        if (dst[qq] < 0) v.y = -v.y;
-                        rect[abs(dst[qq]) - 1] = v;
+                        if (st.fast < 0 || (st.fast == 0 && neg[qq])) v.y = -v.y;
+                        rect[c] = v;
                     }
                 }
             };
@@ -658,10 +691,23 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const float4 e1s = cur.e1s, e2s = cur.e2s, e3s = cur.e3s;
                 // (remainders: read only with exact geometry)
                 const float4 b1 = cur.b1, b2 = cur.b2, b3 = cur.b3;
-                for (int r = 0; r < H; r += 64) {
-                    const int hh = r + lane;
+                // One round: hits r .. r + 64 / K - 1, K lanes per hit (the lanes
+                // of a quad), each evaluating WIN / K rows of the window; the K
+                // partial sums are added across the lanes (DPP within the quad)
+                // and the first lane of each hit updates the voxel's
+                // accumulator.  Full rounds take K = 1; a last round of at most
+                // 32 (16) hits takes K = 2 (4), so its lanes are not left idle.
+                auto round = [&](auto kk, int r) {
+                    constexpr int K = decltype(kk)::value;
+                    constexpr int LK = K == 1 ? 0 : (K == 2 ? 1 : 2);
+                    constexpr int ROWS = WIN / K;
+                    constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0 && K == 1;
+                    const int hh = r + (lane >> LK);
+                    const int part = lane & (K - 1);
+                    float pr = 0.f, pi = 0.f, pw = 0.f;
+                    int lid = 0;
                     if (hh < H) {
-                        const int lid = list_cur[hh];
+                        lid = list_cur[hh];
                         const float vx = static_cast<float>(X0 + (lid & 7));
                         const float vy = static_cast<float>(Y0 + ((lid >> 3) & 7));
                         const float vz = static_cast<float>(Z0 + (lid >> 6));
@@ -674,25 +720,50 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                             uyl = fmaf(b2.x, vx, fmaf(b2.y, vy, b2.z * vz));
                             uz += fmaf(b3.x, vx, fmaf(b3.y, vy, b3.z * vz));
                         }
-                        float pr, pi, pw;
-                        constexpr bool PRE = (FLAGS & SLAB_PRELOAD) != 0;
                         // The rectangle reaches the disk edge: gate each window
                         // cell by |k| < r_max only in rounds where some hit's
-                        // window can reach it.  A window's cells satisfy
-                        // |kx| <= |u_x| + a + 1 (0.1 covers the remainders of
-                        // exact geometry), likewise for y.
+                        // window reaches it, i.e. where the window's farthest
+                        // corner (columns ceil(u_x - a) .. + WIN - 1, likewise
+                        // rows; the window's own origins, remainders included)
+                        // lies outside.
                         bool rim_round = false;
                         if (cur.rim) {
-                            const float ax = fmaf(fabsf(uxs), ts_rinv, g.a + 1.1f);
-                            const float ay = fmaf(fabsf(uys), ts_rinv, g.a + 1.1f);
-                            rim_round = __ballot(fmaf(ax, ax, ay * ay) >= g.r2max) != 0ull;
+                            const float fx0 = ceilf(fmaf(EXACT ? uxs + uxl : uxs, ts_rinv, -g.a));
+                            const float fy0 = ceilf(fmaf(EXACT ? uys + uyl : uys, ts_rinv, -g.a));
+                            const float fx1 = fx0 + static_cast<float>(WIN - 1), fy1 = fy0 + static_cast<float>(WIN - 1);
+                            const float mx = fmaxf(fx0 * fx0, fx1 * fx1), my = fmaxf(fy0 * fy0, fy1 * fy1);
+                            rim_round = __ballot(mx + my >= g.r2max) != 0ull;
                         }
+                        const int j0 = part * ROWS;
                         if (rim_round)
-                            window_lds<WIN, true, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
-                                                                    ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
+                            window_lds<WIN, ROWS, true, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz,
+                                                                          ts_root, ts_rinv, cur.kx_lo, cur.ky_lo,
+                                                                          j0, pr, pi, pw);
                         else
-                            window_lds<WIN, false, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz, ts_root,
-                                                                     ts_rinv, cur.kx_lo, cur.ky_lo, pr, pi, pw);
+                            window_lds<WIN, ROWS, false, MODE, PRE, EXACT>(rect, tab, g, uxs, uxl, uys, uyl, uz,
+                                                                           ts_root, ts_rinv, cur.kx_lo, cur.ky_lo,
+                                                                           j0, pr, pi, pw);
+                    }
+                    if constexpr (K > 1) {
+                        // every lane takes part (idle ones with zeros)
+                        auto swap1 = [](float v) {     // quad_perm [1,0,3,2]
+                            return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF,
+                                                                               false));
+                        };
+                        auto swap2 = [](float v) {     // quad_perm [2,3,0,1]
+                            return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF,
+                                                                               false));
+                        };
+                        pr = swap1(pr);
+                        pi = swap1(pi);
+                        pw = swap1(pw);
+                        if constexpr (K == 4) {
+                            pr = swap2(pr);
+                            pi = swap2(pi);
+                            pw = swap2(pw);
+                        }
+                    }
+                    if (hh < H && part == 0) {
                         // a voxel appears once per slice: single writer within the wave
                         if (FLAGS & SLAB_ATOMIC) {
                             atomicAdd(&acc_c[lid].x, pr);
@@ -706,6 +777,25 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                             acc_w[lid] += pw;
                         }
                     }
+                };
+                const int full = H & ~63;
+                for (int r = 0; r < full; r += 64) round(std::integral_constant<int, 1>{}, r);
+                const int tail = H - full;
+                if (tail > 0) {
+                    bool done = false;
+                    if constexpr (WIN % 4 == 0) {
+                        if (tail <= 16) {
+                            round(std::integral_constant<int, 4>{}, full);
+                            done = true;
+                        }
+                    }
+                    if constexpr (WIN % 2 == 0) {
+                        if (!done && tail <= 32) {
+                            round(std::integral_constant<int, 2>{}, full);
+                            done = true;
+                        }
+                    }
+                    if (!done) round(std::integral_constant<int, 1>{}, full);
                 }
                 wave_sync();
                 if (++inner == inner_chunk) {
