@@ -223,10 +223,12 @@ recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
  * every reconstruction ordered by estimated cost.  recon_batch_insert only
  * enqueues kernels (no host synchronisation, no allocation, no copies), so a
  * caller may capture it in a HIP graph and replay it.  Work runs on the
- * first context's stream.  The launch uses the single-context default
- * configuration of the shared blob (11 waves per work-group for the 4 x 4
- * interpolated window, else 8), and exact window geometry for every box
- * when any box needs it (see recon_insert_batch).
+ * first context's stream.  The launch takes the first context's
+ * configuration at recon_batch_create when it is a slab-kernel one (set with
+ * recon_set_config, or picked by the context's tuner), else the slab
+ * kernel's single-context default for the shared blob (11 waves per
+ * work-group for the 4 x 4 interpolated window, else 8), and exact window
+ * geometry for every box when any box needs it (see recon_insert_batch).
  * --------------------------------------------------------------------- */
 typedef struct recon_batch recon_batch;
 
@@ -280,7 +282,7 @@ typedef struct recon_tune_info {
     int32_t steps_done;         /* configurations measured so far */
     int32_t space_size;         /* configurations in the tuning space */
     int32_t best_index;         /* index of the fastest measured (-1 if none) */
-    double best_ns_per_slice;   /* its insertion-kernel time per slice */
+    double best_ns_per_slice;   /* its insertion time per slice (kernel and partial-sum reduction) */
     double mean_ns_per_slice;   /* mean over the measured configurations */
     recon_config best;          /* the fastest measured configuration */
 } recon_tune_info;
@@ -292,7 +294,8 @@ recon_status recon_tune_space_config(const recon_ctx *ctx, int32_t index, recon_
 
 /* Starts a random search (or a search over the given candidates): the next
  * recon_insert_batch calls each run one untried configuration, timed with
- * events around the insertion kernel.
+ * events around the whole insertion (the insertion kernel and the ordered
+ * reduction of its partial sums, whose cost grows with the split knob).
  * Measuring a step waits for the previous step's kernel (tuning steps are
  * not overlapped, as in the paper's tuning phase).  After max_steps steps, or
  * when the target is met, the fastest configuration is selected and kept. */

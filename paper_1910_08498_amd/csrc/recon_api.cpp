@@ -689,15 +689,16 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
         e = hipEventRecord(c->ev_stop, c->stream);
         if (e != hipSuccess) return hip_fail(e, "record stop event");
     }
-    if (tuning_step) {
-        e = hipEventRecord(c->tune.ev1, c->stream);
-        if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
-    }
     if (c->plan.nslots > 0) {
         e = slab ? recon::launch_reduce_partials8(jt, items + nitems, static_cast<int>(c->plan.ritems.size()),
                                                   c->stream)
                  : recon::launch_reduce_partials(c->g, items, nitems, partials, c->G, c->W, c->stream);
         if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
+    }
+    // a tuning step is timed over the whole insertion: kernel and reduction
+    if (tuning_step) {
+        e = hipEventRecord(c->tune.ev1, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "record tuning stop event");
     }
     return RECON_OK;
 }
@@ -1025,16 +1026,21 @@ struct recon_batch {
 };
 
 // Launch configuration of a batch (the contexts share their blob): the
+// first context's configuration when it is a slab-kernel one (set with
+// recon_set_config or picked by its tuner), else the slab kernel's
 // single-context default, 11 waves with interleaved window reads where that
 // instance exists and fits, else 8 waves with preloaded reads.
 struct BatchLaunch {
-    int wpb, flags, inner, split;
+    int wpb, flags, inner, split, mode;
 };
 static BatchLaunch batch_launch(const recon_ctx *c0)
 {
+    if (c0->cfg.variant == RECON_VARIANT_SLAB)
+        return {c0->cfg.waves_per_block, c0->cfg.slab_flags & 3, c0->cfg.inner_chunk, c0->cfg.split,
+                weight_source(c0->p, c0->cfg.weights)};
     const int mode = weight_source(c0->p, RECON_WEIGHTS_DEFAULT);
-    if (slab_wide_ok(c0->g, mode, c0->max_lds)) return {11, 0, 64, 32};
-    return {8, mode == recon::WEIGHT_OTF ? 0 : 2, 32, 32};
+    if (slab_wide_ok(c0->g, mode, c0->max_lds)) return {11, 0, 64, 32, mode};
+    return {8, mode == recon::WEIGHT_OTF ? 0 : 2, 32, 32, mode};
 }
 
 // Combined work plan of a batch: every context's slab plan (split of the
@@ -1102,8 +1108,7 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     if (ws_bytes < need) return fail(RECON_ENOMEM, "batch workspace too small: %zu given, %zu needed", ws_bytes, need);
     const BatchLaunch bl = batch_launch(ctxs[0]);
     for (int j = 0; j < njobs; ++j)
-        if (recon::slab_lds_bytes(ctxs[j]->g, weight_source(ctxs[j]->p, RECON_WEIGHTS_DEFAULT), bl.wpb) >
-            ctxs[j]->max_lds)
+        if (recon::slab_lds_bytes(ctxs[j]->g, bl.mode, bl.wpb) > ctxs[j]->max_lds)
             return fail(RECON_ECONFIG, "the slab kernel does not fit this device for context %d", j);
     recon_batch *b = new (std::nothrow) recon_batch();
     if (!b) return fail(RECON_ENOMEM, "host allocation failed");
@@ -1115,7 +1120,7 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     b->wpb = bl.wpb;
     b->flags = bl.flags;
     b->inner = bl.inner;
-    b->mode = weight_source(ctxs[0]->p, RECON_WEIGHTS_DEFAULT);
+    b->mode = bl.mode;
     hipStream_t st0 = ctxs[0]->stream;
     hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
     // items, then the split tiles right after them

@@ -79,6 +79,21 @@ class TuneRecord:
     def features(self) -> np.ndarray:
         return features(self.n, self.slices, self.a, self.cus / self.cus_total)
 
+    def save(self, path: str):
+        np.savez(path, n=self.n, slices=self.slices, a=self.a, ns_per_slice=self.ns_per_slice,
+                 keys=np.array(self.keys, dtype=np.int64).reshape(len(self.keys), -1),
+                 default_key=np.array(self.default_key if self.default_key is not None else [], dtype=np.int64),
+                 cus=self.cus, cus_total=self.cus_total)
+
+    @staticmethod
+    def load(path: str) -> "TuneRecord":
+        z = np.load(path)
+        dk = tuple(int(v) for v in z["default_key"]) or None
+        return TuneRecord(n=int(z["n"]), slices=int(z["slices"]), a=float(z["a"]),
+                          ns_per_slice=np.asarray(z["ns_per_slice"], dtype=np.float64),
+                          keys=[tuple(int(v) for v in k) for k in z["keys"]], default_key=dk,
+                          cus=int(z["cus"]), cus_total=int(z["cus_total"]))
+
 
 def union_keys(records) -> list:
     """Configuration keys of all records, in first-seen order."""
@@ -464,6 +479,11 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--portability", action="store_true",
                     help="instead: tune at one box size (or CU count), run at another")
+    ap.add_argument("--records-dir", default=None,
+                    help="keep each workload's timings here (rec_<k>.npz) and reuse the ones present")
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="stop collecting after this many seconds (0: no limit); with --records-dir a "
+                         "later run resumes")
     args = ap.parse_args(argv)
     t0 = time.time()
     if args.portability:
@@ -482,8 +502,21 @@ def main(argv=None):
     records = []
     params = sample_workloads(1000, args.train, n_range=(48, args.n_max)) + \
         sample_workloads(2000, args.test, n_range=(48, args.n_max))
+    import os
+    if args.records_dir:
+        os.makedirs(args.records_dir, exist_ok=True)
     for k, (n, s, a, cus) in enumerate(params):
+        path = os.path.join(args.records_dir, f"rec_{k}.npz") if args.records_dir else None
+        if path and os.path.exists(path):
+            records.append(TuneRecord.load(path))
+            continue
+        if args.time_limit > 0 and time.time() - t0 > args.time_limit:
+            print(f"learned: time limit reached after {k} workloads; run again to resume", file=sys.stderr,
+                  flush=True)
+            return 3
         records.append(time_space(n, s, a, seed=k, batch_cap=args.batch_cap, cus=cus, repeats=args.repeats))
+        if path:
+            records[-1].save(path)
         print(f"learned: workload {k + 1}/{len(params)} n={n} S={s} a={a:.2f} CUs={cus} "
               f"best {records[-1].ns_per_slice.min():.1f} ns/slice ({time.time() - t0:.0f} s)",
               file=sys.stderr, flush=True)

@@ -99,3 +99,16 @@ def test_features_count_slices_per_call():
     f = learned.features(128, 50000, 1.9, 0.5)
     assert f[0] == 7.0 and f[1] == pytest.approx(np.log2(1500)) and f[2] == 1.9 and f[3] == 0.5
     assert learned.features(128, 1000, 1.9, 1.0)[1] == pytest.approx(np.log2(1000))
+
+
+def test_tune_record_round_trip(tmp_path):
+    from paper_1910_08498_amd.learned import TuneRecord
+    r = TuneRecord(n=96, slices=1234, a=1.7, ns_per_slice=np.array([3.0, 2.5, 4.0]),
+                   keys=[(3, 11, 64, 32, 4, 1), (3, 8, 32, 16, 6, 1), (2, 16, 32, 16, 6, 1)],
+                   default_key=(3, 11, 64, 32, 4, 1), cus=128, cus_total=256)
+    r.save(str(tmp_path / "r.npz"))
+    q = TuneRecord.load(str(tmp_path / "r.npz"))
+    assert (q.n, q.slices, q.a, q.cus, q.cus_total) == (96, 1234, 1.7, 128, 256)
+    assert q.keys == r.keys and q.default_key == r.default_key
+    assert np.array_equal(q.ns_per_slice, r.ns_per_slice)
+    assert np.allclose(q.features(), r.features())
