@@ -15,7 +15,9 @@ the measured time per step.  Printed as one JSON line, which also carries
 the roofline of the insertion kernel, the same step with the plain per-voxel
 gather ("plain", and "default_over_plain"), the step with the configuration
 the library's dynamic tuner selects on this workload ("tuned", and
-"tuned_over_plain"), the FP64 oracle timed on a sample of the workload
+"tuned_over_plain"), the step with the interpolation weights evaluated on
+the fly instead of read from the table ("on_the_fly"), the FP64 oracle timed
+on a sample of the workload
 ("cpu_baseline"), and the error of the measured configuration against that
 oracle on the same sample ("error_vs_oracle").  The headline value is the
 library's default configuration, untuned.
@@ -155,6 +157,9 @@ def main(argv=None):
                     help="steps timed with the naive (plain) kernel for comparison (0 disables)")
     ap.add_argument("--tune-steps", type=int, default=50,
                     help="random-search steps of the library's tuner before the tuned leg (0 disables it)")
+    ap.add_argument("--otf-steps", type=int, default=2,
+                    help="steps timed with interpolation weights evaluated on the fly instead of the table "
+                         "(0 disables)")
     ap.add_argument("--h2d-steps", type=int, default=2,
                     help="steps timed with the slices uploaded from pinned host memory (0 disables)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -265,7 +270,8 @@ def main(argv=None):
     tuned = None
     if args.tune_steps > 0:
         tuned = tuned_leg(args, torch, recon, rec, step, nb, w.S, slices, quats, scales, U, ms_per_step)
-        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, weights=0)
+        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
+                       weights=0)
 
     plain = None
     if args.plain_steps > 0 and args.variant != "naive":
@@ -279,6 +285,26 @@ def main(argv=None):
         plain_ms = 1e3 * (time.perf_counter() - t1) / args.plain_steps
         plain = {"value": U / (plain_ms / 1e3), "ms_per_step": plain_ms, "variant": "naive"}
         rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0)
+
+    otf = None
+    if args.otf_steps > 0 and args.workload != "batch8":
+        # the same step with the blob evaluated on the fly (Horner's rule on its
+        # power series) instead of read from the table; the library's default
+        # configuration for that weight source
+        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
+                       weights=recon.RECON_WEIGHTS_OTF)
+        otf_cfg = rec.config()
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.otf_steps):
+            step()
+        torch.cuda.synchronize()
+        otf_ms = 1e3 * (time.perf_counter() - t1) / args.otf_steps
+        otf = {"value": U / (otf_ms / 1e3), "ms_per_step": otf_ms, "config": otf_cfg,
+               "note": "interpolation weights evaluated on the fly (the table leg is value)"}
+        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
+                       weights=0)
 
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
@@ -330,6 +356,7 @@ def main(argv=None):
         "h2d_inclusive": h2d,
         "plain": plain,
         "default_over_plain": None if plain is None else value / plain["value"],
+        "on_the_fly": otf,
         "tuned": tuned,
         "tuned_over_plain": None if plain is None or tuned is None else tuned["value"] / plain["value"],
         "error_vs_oracle": err,

@@ -218,7 +218,7 @@ recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
 
 /* ---------------------------------------------------------------------
  * Batched insertion: several reconstructions (up to 8, any box sizes and
- * slice counts, same blob parameters, same device) inserted by one
+ * slice counts, same blob parameters, slice storage type and device) inserted by one
  * persistent launch of the slab kernel, whose work queue holds the tiles of
  * every reconstruction ordered by estimated cost.  recon_batch_insert only
  * enqueues kernels (no host synchronisation, no allocation, no copies), so a

@@ -1058,6 +1058,8 @@ static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vecto
             p.table_size != q.table_size || p.table_lerp != q.table_lerp)
             return fail(RECON_EINVAL, "batched contexts must share blob parameters (context %d differs)", j);
         if (ctxs[j]->device != ctxs[0]->device) return fail(RECON_EINVAL, "batched contexts must share a device");
+        if (p.slice_dtype != q.slice_dtype)
+            return fail(RECON_EINVAL, "batched contexts must share the slice storage type (context %d differs)", j);
         for (int k = 0; k < j; ++k)
             if (ctxs[k] == ctxs[j]) return fail(RECON_EINVAL, "context %d appears twice", j);
     }

@@ -26,6 +26,7 @@
 //         weight by |k| < r_max.
 //    Steps 1 and the loads of step 2 for the next slice are issued before
 //    step 3 of the current one, so the loads overlap the window evaluation.
+//  * One kernel instance per slice storage type (complex64, half, bfloat16).
 //  * Two-level FP32 accumulation: LDS accumulators hold at most
 //    `inner_chunk` slices before they are folded into per-lane registers.
 //    A tile split into slice ranges writes its parts' sums to partial-sum
@@ -334,7 +335,7 @@ constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 // MAXW: largest work-group (in waves) the instance is built for; it sets the
 // register budget (8 waves: 256 VGPRs, two waves per SIMD; 11 waves: 168
 // VGPRs, three waves on three of the four SIMDs).
-template <int WIN, int MODE, int FLAGS, int MAXW, bool EXACT>
+template <int WIN, int MODE, int FLAGS, int MAXW, bool EXACT, int STORE>
 __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
                                                      const Item *__restrict__ items, int nitems, int inner_chunk,
                                                      Counters *__restrict__ ctr)
@@ -819,12 +820,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 s = s_next;
             }
         };
-        if (g.dtype == 0)
-            slice_loop(std::integral_constant<int, 0>{});
-        else if (g.dtype == 1)
-            slice_loop(std::integral_constant<int, 1>{});
-        else
-            slice_loop(std::integral_constant<int, 2>{});
+        slice_loop(std::integral_constant<int, STORE>{});
 #pragma unroll
         for (int k = 0; k < TV / 64; ++k) {
             const int lid = lane + 64 * k;
@@ -884,8 +880,23 @@ hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *it
     const size_t lds = (static_cast<size_t>(weight_words(jt.job[0].g, MODE)) +
                         static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
     if (wpb > MAXW) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT>), dim3(blocks), dim3(64 * wpb), lds, st, jt, table,
-                       items, nitems, inner_chunk, ctr);
+    // one instance per slice storage type (every job of a launch shares it)
+    switch (jt.job[0].g.dtype) {
+    case 0:
+        hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 0>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
+                           table, items, nitems, inner_chunk, ctr);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 1>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
+                           table, items, nitems, inner_chunk, ctr);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 2>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
+                           table, items, nitems, inner_chunk, ctr);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
