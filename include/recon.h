@@ -91,10 +91,10 @@ typedef struct recon_config {
                                  reads never preloaded; the default where it exists) for
                                  blob radii in [1.5, 2) with table interpolation */
     int32_t group;            /* slices staged per LDS group (binned): 1..16 */
-    int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 (default 32;
-                                 64 with the 11-wave slab default) */
+    int32_t inner_chunk;      /* slices per inner FP32 partial sum: 1..256 (default 64 for
+                                 the slab variant, 32 for the others) */
     int32_t split;            /* max slice-range splits of one tile (binned, slab): 1..64
-                                 (default 16; 32 with the 11-wave slab default) */
+                                 (default 32 for the slab variant, 16 for binned) */
     int32_t slab_flags;       /* slab variant, 4 | bits: bit 0 LDS float atomics for the
                                  accumulators, bit 1 issue all window reads before use
                                  (default 4 | 2; 4 with the 11-wave slab default) */

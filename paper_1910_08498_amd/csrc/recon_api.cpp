@@ -272,6 +272,11 @@ Layout worst_layout(const recon_params &p)
     return layout_for(p, nitems, pv);
 }
 
+// Library default: the slab kernel, 8 waves per work-group with window reads
+// preloaded, inner chunks of 64 slices and up to 32 slice-range splits (the
+// 8-wave configuration of least mean regret over the timed workloads of the
+// learned tuner's data); recon_init takes the 11-wave instance where it
+// applies.  Other variants keep inner chunks of 32 and 16 splits.
 recon_config default_config()
 {
     recon_config c;
@@ -279,11 +284,13 @@ recon_config default_config()
     c.variant = RECON_VARIANT_SLAB;
     c.waves_per_block = 8;
     c.group = 1;
-    c.inner_chunk = 32;
-    c.split = 16;
+    c.inner_chunk = 64;
+    c.split = 32;
     c.slab_flags = 4 | 2;
     return c;
 }
+int default_inner_chunk(int variant) { return variant == RECON_VARIANT_SLAB ? 64 : 32; }
+int default_split(int variant) { return variant == RECON_VARIANT_SLAB ? 32 : 16; }
 
 int default_waves(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 16; }
 
@@ -737,8 +744,8 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
     if (n.waves_per_block == 0) n.waves_per_block = wide ? 11 : default_waves(n.variant);
     if (n.slab_flags == 0 && (n.waves_per_block == 11 || otf)) n.slab_flags = 4;
     if (n.group == 0) n.group = d.group;
-    if (n.inner_chunk == 0) n.inner_chunk = d.inner_chunk;
-    if (n.split == 0) n.split = d.split;
+    if (n.inner_chunk == 0) n.inner_chunk = default_inner_chunk(n.variant);
+    if (n.split == 0) n.split = default_split(n.variant);
     if (n.slab_flags == 0) n.slab_flags = d.slab_flags;
     if (n.slab_flags < 4 || n.slab_flags > 7) return fail(RECON_ECONFIG, "slab_flags must be 4 | bits, bits in [0, 3]");
     if (n.variant != RECON_VARIANT_NAIVE && n.variant != RECON_VARIANT_BINNED && n.variant != RECON_VARIANT_SLAB)
