@@ -106,8 +106,26 @@ typedef struct recon_config {
     int32_t weights;          /* recon_weights: interpolation weights from the table or
                                  evaluated on the fly (the slab variant then runs at most
                                  8 waves and has no window preload) */
-    int32_t reserved[8];
+    int32_t traversal;        /* recon_traversal bits: how the work maps to the tiles
+                                 (default 0) */
+    int32_t reserved[7];
 } recon_config;
+
+/* Traversal of the work (Sect. 4.2, "3D Fourier Reconstruction": the mapping
+ * of work-items to the data inside tiles is a tuning option). */
+typedef enum recon_traversal {
+    /* slab variant: the lanes take a tile's columns (along the dominant axis
+     * of the slice normal) with the second in-plane axis varying fastest;
+     * without it, the first (axes in x, y, z order).  This reorders the hit
+     * list, and so which hits fall into a slice's last round, where a window
+     * sum may be split over 2 or 4 lanes: results change by FP32 rounding. */
+    RECON_TRAVERSAL_COLUMNS_SECOND = 1,
+    /* slab and binned variants: the work queue holds the tiles in spatial
+     * (Morton) order within each of the plan's three cost tiers; without it,
+     * items in decreasing estimated cost.  No result bit changes.  Batched
+     * launches (recon_batch_*) keep the cost order. */
+    RECON_TRAVERSAL_SPATIAL_QUEUE = 2
+} recon_traversal;
 
 /* Source of the interpolation weights (Sect. 4.2, "3D Fourier
  * Reconstruction": precomputed or computed on the fly).  The table holds

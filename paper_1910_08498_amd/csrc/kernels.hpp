@@ -162,10 +162,12 @@ hipError_t launch_reduce_partials(const Geom &g, const Item *items, int nitems,
                                   const float4 *partials, float2 *G, float *W,
                                   hipStream_t st);
 // Slab-enumeration gather over 8x8x8 tiles (one wavefront per item).
+// lane_order: which in-plane axis of a tile's columns varies fastest across
+// the lanes (0: the first, 1: the second).
 size_t slab_lds_bytes(const Geom &g, int mode, int waves_per_block);
 hipError_t launch_insert_slab(const JobTable &jt, int mode, int flags, bool exact, const float2 *table,
-                              const Item *items, int nitems, int inner_chunk, int blocks, int waves_per_block,
-                              Counters *ctr, hipStream_t st);
+                              const Item *items, int nitems, int inner_chunk, int lane_order, int blocks,
+                              int waves_per_block, Counters *ctr, hipStream_t st);
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st);
 hipError_t launch_finalize(const Geom &g, float2 *G, float *W, float2 *V, float thr,
                            hipStream_t st);

@@ -161,8 +161,10 @@ struct Plan {
 // the first 40 % of the cost, are cut into items of twice the target cost,
 // the next 40 % into items of the target, and the cheapest 20 %, which run
 // last, into items of a quarter of it.  Items are ordered by decreasing
-// estimated cost.
-Plan make_plan(const recon_params &p, int split, int E)
+// estimated cost or, with `spatial`, tier by tier with the tiles of a tier
+// in Morton order of their tile coordinates (a tile's parts together, in
+// part order), so that the waves running at one time hold neighbouring tiles.
+Plan make_plan(const recon_params &p, int split, int E, bool spatial)
 {
     Plan plan;
     const int h = p.n / 2, dim = p.n + 1;
@@ -205,11 +207,12 @@ Plan make_plan(const recon_params &p, int split, int E)
     std::vector<int> order(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x].cost > tiles[y].cost; });
-    std::vector<int> np_of(tiles.size());
+    std::vector<int> np_of(tiles.size()), tier_of(tiles.size());
     double cum = 0.0;
     for (int i : order) {
         const double at = cum / std::max(total, 1e-30);
-        const double t = at < 0.4 ? 2.0 * target : (at < 0.8 ? target : std::max(6.0, 0.25 * target));
+        tier_of[i] = at < 0.4 ? 0 : (at < 0.8 ? 1 : 2);
+        const double t = tier_of[i] == 0 ? 2.0 * target : (tier_of[i] == 1 ? target : std::max(6.0, 0.25 * target));
         cum += tiles[i].cost;
         int np = static_cast<int>(std::ceil(tiles[i].cost / t));
         np = std::max(1, std::min(np, split));
@@ -224,6 +227,30 @@ Plan make_plan(const recon_params &p, int split, int E)
         if (np > 1) plan.nslots += np;
         for (int k = 0; k < np; ++k) tmp.push_back({{e.tile, k, np, np > 1 ? slot + k : -1}, e.cost / np});
     }
+    if (spatial) {
+        // key: tier, then the Morton code of (tx, ty, tz) (10 bits each)
+        auto spread = [](uint64_t v) {
+            uint64_t r = 0;
+            for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+            return r;
+        };
+        std::vector<uint64_t> key(tiles.size());
+        for (size_t i = 0; i < tiles.size(); ++i) {
+            const uint64_t t = static_cast<uint64_t>(tiles[i].tile);
+            const uint64_t tx = t % TX, ty = (t / TX) % TY, tz = t / (static_cast<uint64_t>(TX) * TY);
+            key[i] = (static_cast<uint64_t>(tier_of[i]) << 32) | spread(tx) | (spread(ty) << 1) | (spread(tz) << 2);
+        }
+        std::vector<int> by(tiles.size());
+        for (size_t i = 0; i < by.size(); ++i) by[i] = static_cast<int>(i);
+        std::sort(by.begin(), by.end(), [&](int x, int y) { return key[x] < key[y]; });
+        // items of tile i start at the sum of the parts of tiles before it
+        std::vector<size_t> first(tiles.size() + 1, 0);
+        for (size_t i = 0; i < tiles.size(); ++i) first[i + 1] = first[i] + np_of[i];
+        plan.items.reserve(tmp.size());
+        for (int i : by)
+            for (size_t k = first[i]; k < first[i + 1]; ++k) plan.items.push_back(tmp[k].it);
+        return plan;
+    }
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
     plan.items.reserve(tmp.size());
     for (const Tmp &t : tmp) plan.items.push_back(t.it);
@@ -231,6 +258,7 @@ Plan make_plan(const recon_params &p, int split, int E)
 }
 
 int tile_edge(int variant) { return variant == RECON_VARIANT_SLAB ? 8 : 4; }
+bool spatial_queue(const recon_config &c) { return (c.traversal & RECON_TRAVERSAL_SPATIAL_QUEUE) != 0; }
 
 constexpr int kMaxSplit = 64;
 
@@ -264,7 +292,7 @@ Layout layout_for(const recon_params &p, int nitems, size_t partial_vox)
 // Workspace layout large enough for the plan of every variant at the largest split.
 Layout worst_layout(const recon_params &p)
 {
-    Plan p4 = make_plan(p, kMaxSplit, 4), p8 = make_plan(p, kMaxSplit, 8);
+    Plan p4 = make_plan(p, kMaxSplit, 4, false), p8 = make_plan(p, kMaxSplit, 8, false);
     const int nitems = static_cast<int>(std::max(p4.items.size(), p8.items.size()));
     // partial sums per split-tile slot: a float4 per voxel for the binned
     // kernel (64 voxels), three planes of 512 floats for the slab kernel
@@ -564,7 +592,7 @@ recon_status recon_init(const recon_params *p, void *d_G, void *d_W, void *d_ws,
     }
 
     c->L = worst_layout(*p);
-    c->plan = make_plan(*p, c->cfg.split, tile_edge(c->cfg.variant));
+    c->plan = make_plan(*p, c->cfg.split, tile_edge(c->cfg.variant), spatial_queue(c->cfg));
 
     // blob table: entry i = (T[i], T[i+1] - T[i]), T[i] = b(i a^2 / (N-1)), built in FP64;
     // then the polynomial's coefficients (coefficient, 0)
@@ -686,7 +714,8 @@ recon_status recon_insert_batch(recon_ctx *c, const void *d_slices, const float 
         jt.njobs = 1;
         jt.job[0] = {g, slices, orient, rem, partials, c->G, c->W, count, 0};
         e = recon::launch_insert_slab(jt, mode, c->cfg.slab_flags & 3, exact, table, items, nitems,
-                                      c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->stream);
+                                      c->cfg.inner_chunk, c->cfg.traversal & RECON_TRAVERSAL_COLUMNS_SECOND, blocks,
+                                      c->cfg.waves_per_block, ctr, c->stream);
     } else
         e = recon::launch_insert_binned(g, mode, slices, orient, count, table, items, nitems,
                                         partials, c->cfg.inner_chunk, blocks, c->cfg.waves_per_block, ctr, c->G,
@@ -772,6 +801,12 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
                     recon::slab_lds_bytes(c->g, mode, wpb), wpb, c->max_lds);
     if (n.cu_count < 0 || n.cu_count > c->num_cu)
         return fail(RECON_ECONFIG, "cu_count must be in [0, %d] (got %d)", c->num_cu, n.cu_count);
+    if (n.traversal < 0 || n.traversal > 3)
+        return fail(RECON_ECONFIG, "traversal must be a combination of bits 1 and 2 (got %d)", n.traversal);
+    if ((n.traversal & RECON_TRAVERSAL_COLUMNS_SECOND) && n.variant != RECON_VARIANT_SLAB)
+        return fail(RECON_ECONFIG, "the column order of the lanes is a slab-kernel setting");
+    if ((n.traversal & RECON_TRAVERSAL_SPATIAL_QUEUE) && n.variant == RECON_VARIANT_NAIVE)
+        return fail(RECON_ECONFIG, "the naive kernel has no work queue to order");
     *out = n;
     return RECON_OK;
 }
@@ -780,10 +815,11 @@ static recon_status resolve_config(const recon_ctx *c, const recon_config *cfg, 
 // plan when the tiling or the split changes; that upload synchronises).
 static recon_status apply_config(recon_ctx *c, const recon_config &n)
 {
-    const bool replan = n.split != c->cfg.split || tile_edge(n.variant) != tile_edge(c->cfg.variant);
+    const bool replan = n.split != c->cfg.split || tile_edge(n.variant) != tile_edge(c->cfg.variant) ||
+                        spatial_queue(n) != spatial_queue(c->cfg);
     c->cfg = n;
     if (replan) {
-        c->plan = make_plan(c->p, n.split, tile_edge(n.variant));
+        c->plan = make_plan(c->p, n.split, tile_edge(n.variant), spatial_queue(n));
         return upload_plan(c);
     }
     return RECON_OK;
@@ -795,32 +831,39 @@ static std::vector<recon_config> tuning_space(const recon_ctx *c)
     std::vector<recon_config> out;
     const int variants[3] = {RECON_VARIANT_SLAB, RECON_VARIANT_BINNED, RECON_VARIANT_NAIVE};
     for (int v : variants) {
-        std::vector<int> waves = v == RECON_VARIANT_SLAB ? std::vector<int>{4, 8, 11}
+        const bool slab = v == RECON_VARIANT_SLAB;
+        std::vector<int> waves = slab ? std::vector<int>{4, 8, 11}
                                  : v == RECON_VARIANT_BINNED ? std::vector<int>{8, 16}
                                                              : std::vector<int>{4, 8, 16};
         std::vector<int> splits = v == RECON_VARIANT_NAIVE ? std::vector<int>{32} : std::vector<int>{8, 16, 32, 64};
+        // traversal: both bits for the slab kernel, the queue order for the
+        // binned one, none for the naive one
+        std::vector<int> orders = slab ? std::vector<int>{0, 1, 2, 3}
+                                  : v == RECON_VARIANT_BINNED ? std::vector<int>{0, 2} : std::vector<int>{0};
         for (int wt : {RECON_WEIGHTS_TABLE, RECON_WEIGHTS_OTF})
             for (int wpb : waves)
                 for (int inner : {16, 32, 64})
                     for (int sp : splits)
-                        for (int fl : (v != RECON_VARIANT_SLAB ? std::vector<int>{6}
+                        for (int fl : (!slab ? std::vector<int>{6}
                                        : wpb == 11 ? std::vector<int>{4, 5}   // no window preload at 11 waves
-                                                   : std::vector<int>{4, 5, 6, 7})) {
-                            recon_config in;
-                            std::memset(&in, 0, sizeof(in));
-                            in.variant = v;
-                            in.waves_per_block = wpb;
-                            in.group = 1;
-                            in.inner_chunk = inner;
-                            in.split = sp;
-                            in.slab_flags = fl;
-                            in.weights = wt;
-                            in.cu_count = c->cfg.cu_count;   // a property of the stream, not tuned
-                            recon_config r;
-                            const std::string keep = g_err;
-                            if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
-                            g_err = keep;
-                        }
+                                                   : std::vector<int>{4, 5, 6, 7}))
+                            for (int tv : orders) {
+                                recon_config in;
+                                std::memset(&in, 0, sizeof(in));
+                                in.variant = v;
+                                in.waves_per_block = wpb;
+                                in.group = 1;
+                                in.inner_chunk = inner;
+                                in.split = sp;
+                                in.slab_flags = fl;
+                                in.weights = wt;
+                                in.traversal = tv;
+                                in.cu_count = c->cfg.cu_count;   // a property of the stream, not tuned
+                                recon_config r;
+                                const std::string keep = g_err;
+                                if (resolve_config(c, &in, &r) == RECON_OK) out.push_back(r);
+                                g_err = keep;
+                            }
     }
     return out;
 }
@@ -1028,26 +1071,27 @@ struct recon_batch {
     int nitems;
     int nritems;   // split tiles, stored after the items
     size_t off_items;
-    int wpb, flags, inner;   // slab launch configuration of the batch
-    int mode;                // weight source
+    int wpb, flags, inner, lanes;   // slab launch configuration of the batch
+    int mode;                       // weight source
 };
 
 // Launch configuration of a batch (the contexts share their blob): the
 // first context's configuration when it is a slab-kernel one (set with
-// recon_set_config or picked by its tuner), else the slab kernel's
-// single-context default, 11 waves with interleaved window reads where that
-// instance exists and fits, else 8 waves with preloaded reads.
+// recon_set_config or picked by its tuner; its queue-order bit does not
+// apply, the batch's queue interleaves the jobs by cost), else the slab
+// kernel's single-context default, 11 waves with interleaved window reads
+// where that instance exists and fits, else 8 waves with preloaded reads.
 struct BatchLaunch {
-    int wpb, flags, inner, split, mode;
+    int wpb, flags, inner, split, mode, lanes;
 };
 static BatchLaunch batch_launch(const recon_ctx *c0)
 {
     if (c0->cfg.variant == RECON_VARIANT_SLAB)
         return {c0->cfg.waves_per_block, c0->cfg.slab_flags & 3, c0->cfg.inner_chunk, c0->cfg.split,
-                weight_source(c0->p, c0->cfg.weights)};
+                weight_source(c0->p, c0->cfg.weights), c0->cfg.traversal & RECON_TRAVERSAL_COLUMNS_SECOND};
     const int mode = weight_source(c0->p, RECON_WEIGHTS_DEFAULT);
-    if (slab_wide_ok(c0->g, mode, c0->max_lds)) return {11, 0, 64, 32, mode};
-    return {8, mode == recon::WEIGHT_OTF ? 0 : 2, 32, 32, mode};
+    if (slab_wide_ok(c0->g, mode, c0->max_lds)) return {11, 0, 64, 32, mode, 0};
+    return {8, mode == recon::WEIGHT_OTF ? 0 : 2, 32, 32, mode, 0};
 }
 
 // Combined work plan of a batch: every context's slab plan (split of the
@@ -1074,7 +1118,7 @@ static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vecto
     std::vector<Tmp> all;
     const int split = batch_launch(ctxs[0]).split;
     for (int j = 0; j < njobs; ++j) {
-        const Plan pl = make_plan(ctxs[j]->p, split, 8);
+        const Plan pl = make_plan(ctxs[j]->p, split, 8, false);
         // the plan is sorted by cost already; recompute a comparable cost as
         // (slice visits) for interleaving jobs: position-weighted by max_batch
         const size_t n = pl.items.size();
@@ -1129,6 +1173,7 @@ recon_status recon_batch_create(recon_ctx *const *ctxs, int32_t njobs, void *d_w
     b->wpb = bl.wpb;
     b->flags = bl.flags;
     b->inner = bl.inner;
+    b->lanes = bl.lanes;
     b->mode = bl.mode;
     hipStream_t st0 = ctxs[0]->stream;
     hipError_t e = recon::launch_zero(reinterpret_cast<float *>(b->ws), sizeof(Counters) / sizeof(float), st0);
@@ -1186,8 +1231,8 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
-    hipError_t e = recon::launch_insert_slab(jt, b->mode, b->flags, exact, table, items, b->nitems,
-                                             b->inner, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
+    hipError_t e = recon::launch_insert_slab(jt, b->mode, b->flags, exact, table, items, b->nitems, b->inner,
+                                             b->lanes, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
                                              b->wpb, bctr, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items + b->nitems, b->nritems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");

@@ -338,7 +338,7 @@ constexpr int slab_default_flags() { return WIN <= 4 ? SLAB_PRELOAD : 0; }
 template <int WIN, int MODE, int FLAGS, int MAXW, bool EXACT, int STORE>
 __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const float2 *__restrict__ table_g,
                                                      const Item *__restrict__ items, int nitems, int inner_chunk,
-                                                     Counters *__restrict__ ctr)
+                                                     int lane_order, Counters *__restrict__ ctr)
 {
     using SS = SlabShape<WIN>;
     constexpr int RECT = SS::RECT;
@@ -525,7 +525,10 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
                 const int sd = sel3i(d, 1, TE, TE * TE);
                 const int sa = sel3i(ia, 1, TE, TE * TE);
                 const int sb = sel3i(ib, 1, TE, TE * TE);
-                const int ca = lane & (TE - 1), cb = lane >> 3;
+                // lane_order 0: the first in-plane axis varies fastest across the
+                // lanes (and so along the hit list), 1: the second
+                const int cs = lane_order ? 3 : 0;
+                const int ca = (lane >> cs) & (TE - 1), cb = (lane >> (3 - cs)) & (TE - 1);
                 const int va = A0 + ca, vb = B0 + cb;
                 const float fva = static_cast<float>(va), fvb = static_cast<float>(vb);
                 const float rem = R2 - fmaf(fva, fva, fvb * fvb);
@@ -875,7 +878,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
 
 template <int WIN, int MODE, int FLAGS, bool EXACT, int MAXW = 8>
 hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *items, int nitems, int inner_chunk,
-                         int blocks, int wpb, Counters *ctr, hipStream_t st)
+                         int lane_order, int blocks, int wpb, Counters *ctr, hipStream_t st)
 {
     const size_t lds = (static_cast<size_t>(weight_words(jt.job[0].g, MODE)) +
                         static_cast<size_t>(wpb) * SlabShape<WIN>::WAVE_WORDS) * sizeof(float);
@@ -884,15 +887,15 @@ hipError_t launch_slab_t(const JobTable &jt, const float2 *table, const Item *it
     switch (jt.job[0].g.dtype) {
     case 0:
         hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 0>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
-                           table, items, nitems, inner_chunk, ctr);
+                           table, items, nitems, inner_chunk, lane_order, ctr);
         break;
     case 1:
         hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 1>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
-                           table, items, nitems, inner_chunk, ctr);
+                           table, items, nitems, inner_chunk, lane_order, ctr);
         break;
     case 2:
         hipLaunchKernelGGL((k_insert_slab<WIN, MODE, FLAGS, MAXW, EXACT, 2>), dim3(blocks), dim3(64 * wpb), lds, st, jt,
-                           table, items, nitems, inner_chunk, ctr);
+                           table, items, nitems, inner_chunk, lane_order, ctr);
         break;
     default:
         return hipErrorInvalidValue;
@@ -950,21 +953,21 @@ size_t slab_lds_bytes(const Geom &g, int mode, int waves_per_block)
 
 template <bool EXACT>
 static hipError_t dispatch_slab(const JobTable &jt, int mode, int flags, const float2 *table, const Item *items,
-                                int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr, hipStream_t st)
+                                int nitems, int inner_chunk, int lane_order, int blocks, int wpb, Counters *ctr,
+                                hipStream_t st)
 {
+#define RECON_SLAB_ARGS jt, table, items, nitems, inner_chunk, lane_order, blocks, wpb, ctr, st
     const Geom &g = jt.job[0].g;
     const int win = static_cast<int>(floorf(2.0f * g.a)) + 1;
     if (mode == WEIGHT_OTF) {
         // on the fly: 8-wave instances (at most), window reads interleaved;
         // LDS float atomics as a knob for the common window
-        if (win == 4 && (flags & SLAB_ATOMIC))
-            return launch_slab_t<4, WEIGHT_OTF, SLAB_ATOMIC, EXACT>(jt, table, items, nitems, inner_chunk, blocks,
-                                                                    wpb, ctr, st);
+        if (win == 4 && (flags & SLAB_ATOMIC)) return launch_slab_t<4, WEIGHT_OTF, SLAB_ATOMIC, EXACT>(RECON_SLAB_ARGS);
         switch (win) {
-        case 3: return launch_slab_t<3, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 4: return launch_slab_t<4, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 5: return launch_slab_t<5, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 6: return launch_slab_t<6, WEIGHT_OTF, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 3: return launch_slab_t<3, WEIGHT_OTF, 0, EXACT>(RECON_SLAB_ARGS);
+        case 4: return launch_slab_t<4, WEIGHT_OTF, 0, EXACT>(RECON_SLAB_ARGS);
+        case 5: return launch_slab_t<5, WEIGHT_OTF, 0, EXACT>(RECON_SLAB_ARGS);
+        case 6: return launch_slab_t<6, WEIGHT_OTF, 0, EXACT>(RECON_SLAB_ARGS);
         default: return hipErrorInvalidValue;
         }
     }
@@ -973,26 +976,21 @@ static hipError_t dispatch_slab(const JobTable &jt, int mode, int flags, const f
     // linear interpolation; other windows and truncation use the default flags
     if (win == 4 && lerp && wpb > 8) {
         // three waves per SIMD: register budget of 168, window reads interleaved
-        if (flags & SLAB_ATOMIC)
-            return launch_slab_t<4, WEIGHT_LERP, SLAB_ATOMIC, EXACT, 11>(jt, table, items, nitems, inner_chunk,
-                                                                         blocks, wpb, ctr, st);
-        return launch_slab_t<4, WEIGHT_LERP, 0, EXACT, 11>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr,
-                                                           st);
+        if (flags & SLAB_ATOMIC) return launch_slab_t<4, WEIGHT_LERP, SLAB_ATOMIC, EXACT, 11>(RECON_SLAB_ARGS);
+        return launch_slab_t<4, WEIGHT_LERP, 0, EXACT, 11>(RECON_SLAB_ARGS);
     }
     if (win == 4 && lerp) {
         switch (flags & 3) {
-        case 0: return launch_slab_t<4, WEIGHT_LERP, 0, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 1: return launch_slab_t<4, WEIGHT_LERP, 1, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        case 2: return launch_slab_t<4, WEIGHT_LERP, 2, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
-        default: return launch_slab_t<4, WEIGHT_LERP, 3, EXACT>(jt, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+        case 0: return launch_slab_t<4, WEIGHT_LERP, 0, EXACT>(RECON_SLAB_ARGS);
+        case 1: return launch_slab_t<4, WEIGHT_LERP, 1, EXACT>(RECON_SLAB_ARGS);
+        case 2: return launch_slab_t<4, WEIGHT_LERP, 2, EXACT>(RECON_SLAB_ARGS);
+        default: return launch_slab_t<4, WEIGHT_LERP, 3, EXACT>(RECON_SLAB_ARGS);
         }
     }
-#define RECON_SLAB_CASE(WV)                                                                                         \
-    case WV:                                                                                                        \
-        return lerp ? launch_slab_t<WV, WEIGHT_LERP, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,     \
-                                                                                      inner_chunk, blocks, wpb, ctr, st) \
-                    : launch_slab_t<WV, WEIGHT_TRUNC, slab_default_flags<WV>(), EXACT>(jt, table, items, nitems,    \
-                                                                                       inner_chunk, blocks, wpb, ctr, st);
+#define RECON_SLAB_CASE(WV)                                                                                   \
+    case WV:                                                                                                  \
+        return lerp ? launch_slab_t<WV, WEIGHT_LERP, slab_default_flags<WV>(), EXACT>(RECON_SLAB_ARGS)        \
+                    : launch_slab_t<WV, WEIGHT_TRUNC, slab_default_flags<WV>(), EXACT>(RECON_SLAB_ARGS);
     switch (win) {
         RECON_SLAB_CASE(3)
         RECON_SLAB_CASE(4)
@@ -1002,15 +1000,18 @@ static hipError_t dispatch_slab(const JobTable &jt, int mode, int flags, const f
         return hipErrorInvalidValue;
     }
 #undef RECON_SLAB_CASE
+#undef RECON_SLAB_ARGS
 }
 
 hipError_t launch_insert_slab(const JobTable &jt, int mode, int flags, bool exact, const float2 *table,
-                              const Item *items, int nitems, int inner_chunk, int blocks, int wpb, Counters *ctr,
-                              hipStream_t st)
+                              const Item *items, int nitems, int inner_chunk, int lane_order, int blocks, int wpb,
+                              Counters *ctr, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    return exact ? dispatch_slab<true>(jt, mode, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st)
-                 : dispatch_slab<false>(jt, mode, flags, table, items, nitems, inner_chunk, blocks, wpb, ctr, st);
+    return exact ? dispatch_slab<true>(jt, mode, flags, table, items, nitems, inner_chunk, lane_order, blocks, wpb,
+                                       ctr, st)
+                 : dispatch_slab<false>(jt, mode, flags, table, items, nitems, inner_chunk, lane_order, blocks, wpb,
+                                        ctr, st);
 }
 
 hipError_t launch_reduce_partials8(const JobTable &jt, const Item *items, int nitems, hipStream_t st)

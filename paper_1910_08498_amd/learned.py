@@ -19,9 +19,11 @@ Each configuration is timed as the median of several calls, each call a
 whole recon_insert_batch (orientation prep, insertion and the partial-sum
 reduction of split tiles, whose cost the split knob changes), at the batch
 size the library runs.  The predictor's classes are the slab-kernel
-configurations with table weights: the other variants and weights on the
-fly never win on this device, and leaving them out keeps the timing
-collection short.
+configurations with table weights and the default traversal: the other
+variants and weights on the fly never win on this device, the traversal
+settings change a call's time by a few per cent at most, and leaving them
+out keeps the timing collection short (the run-time search still covers
+the traversal knob).
 
 The predictor ranks the configurations; at run time the library's tuner
 then measures its top candidates, and the library's default configuration,
@@ -33,7 +35,7 @@ confident (top probability below a threshold) the tuner falls back to its
 random search.
 
 Configurations are identified by their knob values (variant, waves per
-work-group, inner chunk, split, slab flags, weight source).  The runnable set depends on the
+work-group, inner chunk, split, slab flags, weight source, traversal).  The runnable set depends on the
 workload (some kernel instances exist only for some blob windows), so the
 predictor scores the union of the configurations seen in training and only
 runnable ones are chosen for a workload.
@@ -61,7 +63,17 @@ def features(n: int, slices: int, a: float, cu_frac: float) -> np.ndarray:
 
 def config_key(c) -> tuple:
     return (int(c.variant), int(c.waves_per_block), int(c.inner_chunk), int(c.split), int(c.slab_flags),
-            int(c.weights))
+            int(c.weights), int(c.traversal))
+
+
+KEY_LEN = 7
+
+
+def _key(values) -> tuple:
+    """A stored key as a tuple; keys written before the traversal knob existed
+    (six values) take the default traversal 0."""
+    k = tuple(int(v) for v in values)
+    return k + (0,) * (KEY_LEN - len(k)) if k else k
 
 
 @dataclass
@@ -88,10 +100,10 @@ class TuneRecord:
     @staticmethod
     def load(path: str) -> "TuneRecord":
         z = np.load(path)
-        dk = tuple(int(v) for v in z["default_key"]) or None
+        dk = _key(z["default_key"]) or None
         return TuneRecord(n=int(z["n"]), slices=int(z["slices"]), a=float(z["a"]),
                           ns_per_slice=np.asarray(z["ns_per_slice"], dtype=np.float64),
-                          keys=[tuple(int(v) for v in k) for k in z["keys"]], default_key=dk,
+                          keys=[_key(k) for k in z["keys"]], default_key=dk,
                           cus=int(z["cus"]), cus_total=int(z["cus_total"]))
 
 
@@ -179,8 +191,10 @@ class CUMaskedStream:
 
 
 def slab_table(cfg) -> bool:
-    """The predictor's classes: slab-kernel configurations with table weights."""
-    return int(cfg.variant) == recon.RECON_VARIANT_SLAB and int(cfg.weights) == recon.RECON_WEIGHTS_TABLE
+    """The predictor's classes: slab-kernel configurations with table weights
+    and the default traversal."""
+    return (int(cfg.variant) == recon.RECON_VARIANT_SLAB and int(cfg.weights) == recon.RECON_WEIGHTS_TABLE
+            and int(cfg.traversal) == 0)
 
 
 def time_space(n: int, slices: int, a: float, seed: int, batch_cap: int = CALL_SLICES, device="cuda:0",
@@ -307,7 +321,7 @@ def load_predictor(path: str, device="cuda:0"):
     norm = Normalizer(np.zeros((1, model.n_in)))
     norm.mu, norm.sd = z["mu"], z["sd"]
     model.norm = norm
-    return model, [tuple(int(v) for v in k) for k in z["keys"]]
+    return model, [_key(k) for k in z["keys"]]
 
 
 def regret(ns: np.ndarray, choice: np.ndarray) -> np.ndarray:

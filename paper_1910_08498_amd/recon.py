@@ -19,6 +19,7 @@ RECON_OK, RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ECONFIG = 0, -1, -2, 
 RECON_SLICE_C64, RECON_SLICE_F16, RECON_SLICE_BF16 = 0, 1, 2
 RECON_VARIANT_AUTO, RECON_VARIANT_NAIVE, RECON_VARIANT_BINNED, RECON_VARIANT_SLAB = 0, 1, 2, 3
 RECON_WEIGHTS_DEFAULT, RECON_WEIGHTS_TABLE, RECON_WEIGHTS_OTF = 0, 1, 2
+RECON_TRAVERSAL_COLUMNS_SECOND, RECON_TRAVERSAL_SPATIAL_QUEUE = 1, 2
 
 
 class recon_params(ctypes.Structure):
@@ -32,7 +33,7 @@ class recon_config(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("inner_chunk", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("slab_flags", ctypes.c_int32), ("cu_count", ctypes.c_int32), ("weights", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("traversal", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class recon_tune_opts(ctypes.Structure):

@@ -28,7 +28,7 @@ def test_tuning_space_is_runnable(env):
     for i in range(n):
         c = recon.recon_tune_space_config(rec.ctx, i)
         recon.recon_set_config(rec.ctx, c)      # every member is accepted
-        seen.add((c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags, c.weights))
+        seen.add((c.variant, c.waves_per_block, c.inner_chunk, c.split, c.slab_flags, c.weights, c.traversal))
     assert len(seen) == n
     with pytest.raises(recon.ReconError):
         recon.recon_tune_space_config(rec.ctx, n)
@@ -51,8 +51,8 @@ def test_full_search_keeps_parity_and_selects_best(env):
     assert 0 <= info.best_index < size
     assert 0 < info.best_ns_per_slice <= info.mean_ns_per_slice
     cur = recon.recon_get_config(rec.ctx)
-    assert (cur.variant, cur.waves_per_block, cur.inner_chunk, cur.split, cur.slab_flags) == \
-        (info.best.variant, info.best.waves_per_block, info.best.inner_chunk, info.best.split, info.best.slab_flags)
+    key = ("variant", "waves_per_block", "inner_chunk", "split", "slab_flags", "weights", "traversal")
+    assert [getattr(cur, k) for k in key] == [getattr(info.best, k) for k in key]
     G, W, U = oracle.insert(w.n, w.slices, w.quats)
     Vo = oracle.finalize(G, W)
     eg = oracle.rel_l2(rec.G.cpu().numpy(), G)

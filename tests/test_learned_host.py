@@ -104,11 +104,24 @@ def test_features_count_slices_per_call():
 def test_tune_record_round_trip(tmp_path):
     from paper_1910_08498_amd.learned import TuneRecord
     r = TuneRecord(n=96, slices=1234, a=1.7, ns_per_slice=np.array([3.0, 2.5, 4.0]),
-                   keys=[(3, 11, 64, 32, 4, 1), (3, 8, 32, 16, 6, 1), (2, 16, 32, 16, 6, 1)],
-                   default_key=(3, 11, 64, 32, 4, 1), cus=128, cus_total=256)
+                   keys=[(3, 11, 64, 32, 4, 1, 0), (3, 8, 32, 16, 6, 1, 3), (2, 16, 32, 16, 6, 1, 2)],
+                   default_key=(3, 11, 64, 32, 4, 1, 0), cus=128, cus_total=256)
     r.save(str(tmp_path / "r.npz"))
     q = TuneRecord.load(str(tmp_path / "r.npz"))
     assert (q.n, q.slices, q.a, q.cus, q.cus_total) == (96, 1234, 1.7, 128, 256)
     assert q.keys == r.keys and q.default_key == r.default_key
     assert np.array_equal(q.ns_per_slice, r.ns_per_slice)
     assert np.allclose(q.features(), r.features())
+
+
+def test_tune_record_keys_without_traversal_load_with_the_default(tmp_path):
+    """Records written before the traversal knob hold six-value keys; they
+    load with traversal 0, the only value those timings covered."""
+    from paper_1910_08498_amd.learned import TuneRecord
+    r = TuneRecord(n=64, slices=500, a=1.9, ns_per_slice=np.array([1.0, 2.0]),
+                   keys=[(3, 11, 64, 32, 4, 1), (3, 8, 32, 16, 6, 1)], default_key=(3, 11, 64, 32, 4, 1),
+                   cus=256, cus_total=256)
+    r.save(str(tmp_path / "old.npz"))
+    q = TuneRecord.load(str(tmp_path / "old.npz"))
+    assert q.keys == [(3, 11, 64, 32, 4, 1, 0), (3, 8, 32, 16, 6, 1, 0)]
+    assert q.default_key == (3, 11, 64, 32, 4, 1, 0)
