@@ -550,7 +550,36 @@ def bench_batch8(args) -> int:
     side.synchronize()
     ms = timed(graph.replay)
     ms_sep = timed(step_separate)
-    U = int(counts["U"])
+    U, U_half = int(counts["U"]), int(counts["U_half"])
+
+    # the batched insertion kernel's own duration, per launch: events on the
+    # launch stream around the kernel alone (the first context's timing
+    # events), over eager runs of the step's rounds
+    kev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(rounds)]
+           for _ in range(max(1, args.steps))]
+    c0 = jobs[0]["rec"].ctx
+    with torch.cuda.stream(side):
+        for row in kev:                           # torch creates the HIP events on first record
+            for e0, e1 in row:
+                e0.record(side)
+                e1.record(side)
+        side.synchronize()
+        for row in kev:
+            for j in jobs:
+                j["rec"].reset()
+            for (sls, qts, cnt), (e0, e1) in zip(prepared, row):
+                recon.recon_set_timing_events(c0, e0, e1)
+                recon.recon_batch_insert(b, sls, None, qts, cnt)
+            recon.recon_set_timing_events(c0, None, None)
+        side.synchronize()
+    kernel_ms = np.array([[e0.elapsed_time(e1) for e0, e1 in row] for row in kev])     # [steps, rounds]
+    kernel_ms_per_step = float(kernel_ms.sum(axis=1).mean())
+    achieved_tflops = FLOPS_PER_UPDATE * U_half / (kernel_ms_per_step / 1e3) / 1e12
+    # algorithmic bytes: every slice read once; every launch reads and writes
+    # each box's half of G (8 B) and W (4 B)
+    slice_bytes = sum(j["w"].S * j["w"].n * (j["w"].n // 2 + 1) * 8 for j in jobs)
+    gw_rmw = sum(2 * 12 * (j["w"].n // 2 + 1) * (j["w"].n + 1) ** 2 for j in jobs) * rounds
+    hbm_gbps = (slice_bytes + gw_rmw) / (kernel_ms_per_step / 1e3) / 1e9
 
     # each reconstruction's first slices, through the same batched launch, against the oracle
     k = 120
@@ -589,7 +618,22 @@ def bench_batch8(args) -> int:
                               "launches_per_round": len(jobs)},
         "error_vs_oracle": {"per_job": errs, "bound": 1e-5,
                             "sample": f"first {k} slices of each reconstruction, one batched launch, whole volumes"},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_insert_slab",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": float(kernel_ms.mean()),
+            "launches_per_step": rounds,
+            "flops_per_update": FLOPS_PER_UPDATE,
+            "pairs_half_box": U_half,
+            "hbm_alg_GBps": hbm_gbps,
+            "hbm_alg_frac": hbm_gbps / PEAK_HBM_GBPS,
+        },
+        "cpu_baseline": None,
     }
     print(json.dumps(result), flush=True)
     recon.recon_batch_destroy(b)

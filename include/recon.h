@@ -231,7 +231,9 @@ recon_status recon_set_stream(recon_ctx *ctx, void *stream);
 /* Timing hook for measurement: when start/stop are non-NULL hipEvent_t
  * handles, the next recon_insert_batch calls record `start` on the context's
  * stream immediately before the main insertion kernel and `stop` immediately
- * after it (prep and partial-sum kernels excluded).  NULL, NULL disables. */
+ * after it (prep and partial-sum kernels excluded); recon_batch_insert does
+ * the same around its one insertion kernel with the events of its first
+ * context.  NULL, NULL disables. */
 recon_status recon_set_timing_events(recon_ctx *ctx, void *start, void *stop);
 
 /* ---------------------------------------------------------------------

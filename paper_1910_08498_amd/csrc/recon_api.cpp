@@ -1231,9 +1231,15 @@ recon_status recon_batch_insert(recon_batch *b, const void *const *d_slices, con
     const Item *items = reinterpret_cast<const Item *>(b->ws + b->off_items);
     recon_ctx *c0 = b->ctxs[0];
     const float2 *table = reinterpret_cast<const float2 *>(c0->ws + c0->L.table);
+    // the first context's timing events, if set, bracket the batched kernel
+    if (c0->ev_start) {
+        hipError_t er = hipEventRecord(c0->ev_start, st);
+        if (er != hipSuccess) return hip_fail(er, "record start event");
+    }
     hipError_t e = recon::launch_insert_slab(jt, b->mode, b->flags, exact, table, items, b->nitems, b->inner,
                                              b->lanes, c0->cfg.cu_count > 0 ? c0->cfg.cu_count : c0->num_cu,
                                              b->wpb, bctr, st);
+    if (e == hipSuccess && c0->ev_stop) e = hipEventRecord(c0->ev_stop, st);
     if (e == hipSuccess) e = recon::launch_reduce_partials8(jt, items + b->nitems, b->nritems, st);
     if (e != hipSuccess) return hip_fail(e, "batch insert launch");
     return RECON_OK;
