@@ -145,6 +145,7 @@ recon_status validate(const recon_params *p)
 // ---------------------------------------------------------------------------
 struct Plan {
     std::vector<Item> items;
+    std::vector<double> cost;   // estimated cost of each item (slice visits)
     std::vector<Item> ritems;   // split tiles (uploaded after the items)
     int nslots = 0;
 };
@@ -247,13 +248,21 @@ Plan make_plan(const recon_params &p, int split, int E, bool spatial)
         std::vector<size_t> first(tiles.size() + 1, 0);
         for (size_t i = 0; i < tiles.size(); ++i) first[i + 1] = first[i] + np_of[i];
         plan.items.reserve(tmp.size());
+        plan.cost.reserve(tmp.size());
         for (int i : by)
-            for (size_t k = first[i]; k < first[i + 1]; ++k) plan.items.push_back(tmp[k].it);
+            for (size_t k = first[i]; k < first[i + 1]; ++k) {
+                plan.items.push_back(tmp[k].it);
+                plan.cost.push_back(tmp[k].cost);
+            }
         return plan;
     }
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });
     plan.items.reserve(tmp.size());
-    for (const Tmp &t : tmp) plan.items.push_back(t.it);
+    plan.cost.reserve(tmp.size());
+    for (const Tmp &t : tmp) {
+        plan.items.push_back(t.it);
+        plan.cost.push_back(t.cost);
+    }
     return plan;
 }
 
@@ -1095,9 +1104,9 @@ static BatchLaunch batch_launch(const recon_ctx *c0)
 }
 
 // Combined work plan of a batch: every context's slab plan (split of the
-// batch's launch configuration),
-// tagged with its job index in the tile field's top byte, in decreasing
-// estimated cost across all jobs.
+// batch's launch configuration), tagged with its job index in the tile
+// field's top byte, in decreasing estimated cost across all jobs (the plans'
+// own cost estimates, in slice visits).
 static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vector<Item> *items)
 {
     if (!ctxs || njobs < 1 || njobs > recon::kMaxJobs)
@@ -1118,17 +1127,14 @@ static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vecto
     std::vector<Tmp> all;
     const int split = batch_launch(ctxs[0]).split;
     for (int j = 0; j < njobs; ++j) {
+        // each job's own plan (its partial-sum slots fit its workspace); the
+        // items of all jobs are then ordered by their estimated cost
         const Plan pl = make_plan(ctxs[j]->p, split, 8, false);
-        // the plan is sorted by cost already; recompute a comparable cost as
-        // (slice visits) for interleaving jobs: position-weighted by max_batch
-        const size_t n = pl.items.size();
-        for (size_t i = 0; i < n; ++i) {
+        for (size_t i = 0; i < pl.items.size(); ++i) {
             Item it = pl.items[i];
             if (it.tile >= (1 << 24)) return fail(RECON_EINVAL, "box too large for a batch");
             it.tile |= j << 24;
-            const double cost = static_cast<double>(ctxs[j]->p.max_batch) / it.nparts *
-                                (1.0 - 0.5 * static_cast<double>(i) / std::max<size_t>(n, 1));
-            all.push_back({it, cost});
+            all.push_back({it, pl.cost[i]});
         }
     }
     std::stable_sort(all.begin(), all.end(), [](const Tmp &x, const Tmp &y) { return x.cost > y.cost; });

@@ -382,6 +382,10 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
         const Item item = items[it];
         // the item's reconstruction (job) and its geometry and buffers
         const int job = __builtin_amdgcn_readfirstlane(item.tile >> 24);
+        // a job without slices in this launch (a batch whose reconstructions
+        // hold different slice counts) adds nothing: its items and their
+        // partial sums are skipped
+        if (jt.job[job].count == 0) continue;
         const int tile = item.tile & 0xffffff;
         const Geom g = jt.job[job].g;
         const void *__restrict__ slices = jt.job[job].slices;
@@ -910,6 +914,7 @@ __global__ __launch_bounds__(512) void k_reduce_partials8(JobTable jt, const Ite
     const Item item = items[blockIdx.x];
     if (item.nparts == 1 || item.part != 0) return;
     const int job = item.tile >> 24;
+    if (jt.job[job].count == 0) return;    // skipped by the insertion kernel too
     const int tile = item.tile & 0xffffff;
     const Geom g = jt.job[job].g;
     const float *__restrict__ partials = reinterpret_cast<const float *>(jt.job[job].partials);
