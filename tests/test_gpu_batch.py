@@ -104,3 +104,46 @@ def test_batch_insert_replays_from_graph(env):
     recon.recon_batch_destroy(b)
     for j in jobs:
         j[1].close()
+
+
+def test_batch_rounds_with_reconstructions_that_run_out(env):
+    """Several batched rounds where the reconstructions run out of slices at
+    different rounds: a job with no slices in a round is skipped by the
+    launch (its items and partial sums), and what it already holds must
+    stay, so each reconstruction still equals its oracle."""
+    torch, dev, recon = env
+    stream = torch.cuda.current_stream()
+    specs = [(40, 120), (32, 30), (48, 75)]
+    per = 50
+    jobs = []
+    for k, (n, S) in enumerate(specs):
+        w = synth.make_workload("small", n=n, S=S, K=6, seed_phantom=110 + k, seed_orient=120 + k)
+        rec = recon.Reconstruction(n, device=dev, stream=stream, max_batch=per)
+        rec.set_config(split=64)      # many split tiles, so partial sums are in play
+        jobs.append((w, rec, torch.from_numpy(w.slices).to(dev), torch.from_numpy(w.quats).to(dev)))
+    ctxs = [j[1].ctx for j in jobs]
+    ws = torch.empty(recon.recon_batch_query_size(ctxs), dtype=torch.uint8, device=dev)
+    b = recon.recon_batch_create(ctxs, ws)
+    rounds = max((S + per - 1) // per for _, S in specs)
+    print(f"[gpu] batch rounds {rounds} over {specs}, {per} slices per round", flush=True)
+    for r in range(rounds):
+        sls, qts, cnt = [], [], []
+        for w, _, sl, q in jobs:
+            s0, s1 = min(w.S, r * per), min(w.S, (r + 1) * per)
+            sls.append(sl[s0:s1] if s1 > s0 else None)
+            qts.append(q[s0:s1] if s1 > s0 else None)
+            cnt.append(s1 - s0)
+        recon.recon_batch_insert(b, sls, None, qts, cnt)
+    for w, rec, _, _ in jobs:
+        V = rec.finalize()
+        torch.cuda.synchronize()
+        G, W, U = oracle.insert(w.n, w.slices, w.quats)
+        eg = oracle.rel_l2(rec.G.cpu().numpy(), G)
+        ew = oracle.rel_l2(rec.W.cpu().numpy(), W)
+        ev = oracle.rel_l2(V.cpu().numpy(), oracle.finalize(G, W))
+        print(f"   n={w.n} S={w.S}: G={eg:.2e} W={ew:.2e} V={ev:.2e}", flush=True)
+        assert max(eg, ew, ev) <= 1e-5
+        assert rec.stats() == (w.S, 0)
+    recon.recon_batch_destroy(b)
+    for j in jobs:
+        j[1].close()
