@@ -162,6 +162,9 @@ def main(argv=None):
                          "(0 disables)")
     ap.add_argument("--h2d-steps", type=int, default=2,
                     help="steps timed with the slices uploaded from pinned host memory (0 disables)")
+    ap.add_argument("--traversal", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="recon_config.traversal of the measured configuration (slab: lanes' column order, "
+                         "bit 0; spatial work queue, bit 1)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB after timing (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -213,7 +216,16 @@ def main(argv=None):
     rec = recon.Reconstruction(w.n, device=dev, max_batch=args.batch, slice_dtype=sdt)
     variant_ids = {"slab": recon.RECON_VARIANT_SLAB, "binned": recon.RECON_VARIANT_BINNED,
                    "naive": recon.RECON_VARIANT_NAIVE}
-    rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0)
+
+    def set_default(**extra):
+        # the measured configuration: the library's defaults for the variant
+        # (every knob a leg may have changed), with the requested traversal
+        cfg = dict(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
+                   weights=0, traversal=args.traversal)
+        cfg.update(extra)
+        rec.set_config(**cfg)
+
+    set_default()
     V = torch.empty_like(rec.G)
     nb = (w.S + args.batch - 1) // args.batch
     stream = torch.cuda.current_stream()
@@ -270,12 +282,11 @@ def main(argv=None):
     tuned = None
     if args.tune_steps > 0:
         tuned = tuned_leg(args, torch, recon, rec, step, nb, w.S, slices, quats, scales, U, ms_per_step)
-        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
-                       weights=0)
+        set_default()
 
     plain = None
     if args.plain_steps > 0 and args.variant != "naive":
-        rec.set_config(variant=recon.RECON_VARIANT_NAIVE, waves_per_block=0, slab_flags=0)
+        set_default(variant=recon.RECON_VARIANT_NAIVE, traversal=0)
         step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -284,15 +295,14 @@ def main(argv=None):
         torch.cuda.synchronize()
         plain_ms = 1e3 * (time.perf_counter() - t1) / args.plain_steps
         plain = {"value": U / (plain_ms / 1e3), "ms_per_step": plain_ms, "variant": "naive"}
-        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0)
+        set_default()
 
     otf = None
     if args.otf_steps > 0 and args.workload != "batch8":
         # the same step with the blob evaluated on the fly (Horner's rule on its
         # power series) instead of read from the table; the library's default
         # configuration for that weight source
-        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
-                       weights=recon.RECON_WEIGHTS_OTF)
+        set_default(weights=recon.RECON_WEIGHTS_OTF)
         otf_cfg = rec.config()
         step()
         torch.cuda.synchronize()
@@ -303,8 +313,7 @@ def main(argv=None):
         otf_ms = 1e3 * (time.perf_counter() - t1) / args.otf_steps
         otf = {"value": U / (otf_ms / 1e3), "ms_per_step": otf_ms, "config": otf_cfg,
                "note": "interpolation weights evaluated on the fly (the table leg is value)"}
-        rec.set_config(variant=variant_ids[args.variant], waves_per_block=0, slab_flags=0, inner_chunk=0, split=0,
-                       weights=0)
+        set_default()
 
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
@@ -338,7 +347,8 @@ def main(argv=None):
         "data": "synthetic: seeded 40-Gaussian phantom projections (exact line integrals) and their centered "
                 "DFTs, Haar-uniform orientations; stands in for EMPIAR-10010",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "n": w.n, "slices": w.S, "batch": args.batch,
-                   "variant": args.variant, "slice_storage": args.dtype, "pairs_U": U, "pairs_half_box": U_half},
+                   "variant": args.variant, "slice_storage": args.dtype, "traversal": args.traversal,
+                   "pairs_U": U, "pairs_half_box": U_half},
         "roofline": {
             "bound": "alu",
             "kernel": {"slab": "k_insert_slab", "binned": "k_insert_binned", "naive": "k_insert_naive"}[args.variant],
