@@ -285,7 +285,8 @@ typedef struct recon_tune_opts {
     int32_t reserved0;
     uint64_t seed;              /* seed of the random search order */
     double target_ns_per_slice; /* stop early once a configuration reaches this
-                                   insertion-kernel time per slice (0 = never) */
+                                   insertion time per slice, kernel and partial-sum
+                                   reduction (0 = never) */
     int32_t order_count;        /* candidates: when order is not NULL, the search tries
                                    the tuning-space indices order[0..order_count-1] in
                                    that order (distinct, each in [0, space size)) instead
