@@ -374,10 +374,13 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
     float *acc_w = accs + 2 * TV;
     unsigned short *list = reinterpret_cast<unsigned short *>(wregion + 2 * RECT2 + ACC_WORDS);
 
+    // Queue positions are taken by lane 0; an item's successor is taken
+    // before the item's final writes, so the atomic's round trip overlaps
+    // them.  Every wave ends on a position at or past nitems.
+    unsigned pos = 0;
+    if (lane == 0) pos = atomicAdd(&ctr->queue, 1u);
     for (;;) {
-        unsigned it = 0;
-        if (lane == 0) it = atomicAdd(&ctr->queue, 1u);
-        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+        const unsigned it = __builtin_amdgcn_readfirstlane(pos);
         if (it >= static_cast<unsigned>(nitems)) break;
         const Item item = items[it];
         // the item's reconstruction (job) and its geometry and buffers
@@ -385,7 +388,10 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
         // a job without slices in this launch (a batch whose reconstructions
         // hold different slice counts) adds nothing: its items and their
         // partial sums are skipped
-        if (jt.job[job].count == 0) continue;
+        if (jt.job[job].count == 0) {
+            if (lane == 0) pos = atomicAdd(&ctr->queue, 1u);
+            continue;
+        }
         const int tile = item.tile & 0xffffff;
         const Geom g = jt.job[job].g;
         const void *__restrict__ slices = jt.job[job].slices;
@@ -837,6 +843,7 @@ __global__ __launch_bounds__(64 * MAXW) void k_insert_slab(JobTable jt, const fl
             ow[k] += acc_w[lid];
         }
         wave_sync();
+        if (lane == 0) pos = atomicAdd(&ctr->queue, 1u);
         if (item.nparts == 1) {
             // all reads first, then all writes: G and W may not be proven
             // disjoint, and interleaving would serialise every read
