@@ -165,7 +165,10 @@ struct Plan {
 // estimated cost or, with `spatial`, tier by tier with the tiles of a tier
 // in Morton order of their tile coordinates (a tile's parts together, in
 // part order), so that the waves running at one time hold neighbouring tiles.
-Plan make_plan(const recon_params &p, int split, int E, bool spatial)
+// `launch_total`, when positive, is the estimated cost of the whole launch
+// the plan is part of (a batch of reconstructions): the item sizes follow
+// it rather than this reconstruction's own total.
+Plan make_plan(const recon_params &p, int split, int E, bool spatial, double launch_total = 0.0)
 {
     Plan plan;
     const int h = p.n / 2, dim = p.n + 1;
@@ -204,7 +207,7 @@ Plan make_plan(const recon_params &p, int split, int E, bool spatial)
     // target item cost: an eighth of the mean cost per wavefront slot of a
     // 256-CU device (16 slots per CU for 4^3 tiles, 8 for 8^3), >= 24 visits
     const double slots = 256.0 * (E == 4 ? 16.0 : 8.0);
-    const double target = std::max(24.0, total / (slots * 8.0));
+    const double target = std::max(24.0, std::max(total, launch_total) / (slots * 8.0));
     std::vector<int> order(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tiles[x].cost > tiles[y].cost; });
@@ -1126,10 +1129,20 @@ static recon_status batch_plan(recon_ctx *const *ctxs, int32_t njobs, std::vecto
     struct Tmp { Item it; double cost; };
     std::vector<Tmp> all;
     const int split = batch_launch(ctxs[0]).split;
+    // Item sizes follow the cost of the whole launch, not each job's alone
+    // (a larger target gives each tile at most as many parts, so every job's
+    // partial-sum slots still fit its workspace); the items of all jobs are
+    // then ordered by their estimated cost.
+    double launch_total = 0.0;
+    for (int j = 0; j < njobs; ++j)
+        for (double c : make_plan(ctxs[j]->p, split, 8, false).cost) launch_total += c;
     for (int j = 0; j < njobs; ++j) {
-        // each job's own plan (its partial-sum slots fit its workspace); the
-        // items of all jobs are then ordered by their estimated cost
-        const Plan pl = make_plan(ctxs[j]->p, split, 8, false);
+        const Plan pl = make_plan(ctxs[j]->p, split, 8, false, launch_total);
+        // slots of three planes of 512 floats in the job's workspace
+        const size_t cap = (ctxs[j]->L.total - ctxs[j]->L.partials) / (384 * sizeof(float4));
+        if (static_cast<size_t>(pl.nslots) > cap)
+            return fail(RECON_ECONFIG, "batch plan of context %d needs %d partial-sum slots (workspace: %zu)", j,
+                        pl.nslots, cap);
         for (size_t i = 0; i < pl.items.size(); ++i) {
             Item it = pl.items[i];
             if (it.tile >= (1 << 24)) return fail(RECON_EINVAL, "box too large for a batch");
